@@ -1,0 +1,224 @@
+"""Pins for the oracle's noise generator, integrator, schedules, dCCI rules
+and estimators.  Each check is fixed by something outside the oracle's code:
+numpy's own Philox, conservation laws, exact free energies of harmonic
+crystals, textbook ideal-gas NPT statistics, and closed forms of the paper's
+switching relations.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2103_10449_amd import inputs
+
+
+# ---------------------------------------------------------------- Philox -----
+@pytest.mark.parametrize("key,ctr", [
+    ((1, 2), (0, 0, 0, 0)),
+    ((0xDEADBEEFCAFEF00D, 7), (5, 9, 0, 0)),
+    ((210310449, 63), (123456789012, 13823, 0, 0)),
+    ((0xFFFFFFFFFFFFFFFF, 0xFFFFFFFFFFFFFFFF), (0xFFFFFFFFFFFFFFFE, 3, 4, 5)),
+])
+def test_philox_matches_numpy(key, ctr):
+    """numpy's Philox bit generator is Philox4x64-10; it increments the
+    counter before producing a block, so its first block is ours at ctr+1."""
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(ctr, dtype=np.uint64))
+    raw = [int(w) for w in g.random_raw(4)]
+    with np.errstate(over="ignore"):
+        c = [np.uint64(ctr[0]) + np.uint64(1)] + [np.uint64(c) for c in ctr[1:]]
+    ours = [int(w) for w in orc.philox4x64(c, key)]
+    assert ours == raw
+
+
+def test_normals_statistics_and_determinism():
+    z = orc.normals(11, 3, 7, 200000)
+    assert abs(z.mean()) < 0.01
+    assert z.var() == pytest.approx(1.0, abs=0.01)
+    assert np.array_equal(z, orc.normals(11, 3, 7, 200000))
+    assert not np.array_equal(z[:10], orc.normals(11, 3, 8, 10))
+
+
+# ------------------------------------------------------------ integrator -----
+def _c1_system(mode=orc.MODE_NVE, **kw):
+    wl = inputs.config1()
+    s = wl.systems[0]
+    return orc.OSystem(x=s.x, v=s.v, box=s.box, mode=mode, x0=s.x0, **kw)
+
+
+def test_nve_energy_conservation(sw_params):
+    """Velocity Verlet without thermostat/barostat conserves K + U: over 2 ps at
+    1 fs the deviation stays well below 1e-4 eV/atom with no secular drift."""
+    s = _c1_system()
+    o = orc.Oracle([s], sw_params, dt=0.001)
+    E0 = s.U_int + s.kinetic()
+    es = []
+    for _ in range(2000):
+        o.step()
+        es.append(s.U_int + s.kinetic())
+    es = (np.array(es) - E0) / s.n
+    assert np.abs(es).max() < 1e-4
+    drift = abs(es[-500:].mean() - es[:500].mean())
+    assert drift < 2e-5
+    # no thermostat and Sum F = 0: total momentum stays zero
+    assert np.abs(s.v.sum(axis=0)).max() < 1e-9
+
+
+def test_zero_sum_noise_conserves_momentum_and_thermalises(sw_params):
+    s = _c1_system(mode=orc.MODE_NVT, T0=1000.0, tau_damp=0.1, stream=4)
+    o = orc.Oracle([s], sw_params, dt=0.001, seed=2)
+    Ts = []
+    for i in range(3000):
+        o.step()
+        if i >= 500:
+            Ts.append(s.temperature())
+    assert np.abs(s.v.sum(axis=0)).max() < 1e-9
+    assert np.mean(Ts) == pytest.approx(1000.0, rel=0.05)
+
+
+def test_einstein_switching_free_energy(sw_params):
+    """Frenkel-Ladd switching between two Einstein crystals (SW off): H_lambda =
+    (1 - lambda) U_E(k), lambda 0 -> 1/2, i.e. springs k -> k/2.  With the
+    centre of mass fixed there are N - 1 independent 3D oscillators, so
+    Delta F = (3 (N - 1) / 2) kB T ln(1/2) exactly (section 2.1 estimator)."""
+    P = dict(sw_params)
+    P["epsilon"] = 0.0
+    T, k, lam_e, nst, nrep = 1000.0, 5.0, 0.5, 1000, 8
+    x0, box = inputs.diamond((2, 2, 2), 5.431)
+    W = {0: [], 1: []}
+    for rep in range(nrep):
+        for d in (0, 1):
+            lam0 = 0.0 if d == 0 else lam_e
+            x = inputs.perturb(x0, np.sqrt(orc.KB * T / ((1 - lam0) * k)), inputs.rng(950, rep, d))
+            v = inputs.maxwell(64, T, inputs.rng(950, rep, 10 + d))
+            s = orc.OSystem(x=x, v=v, box=box, mode=orc.MODE_FL, x0=x0, k_spring=k, T0=T,
+                            tau_damp=0.1, stream=2 * rep + d, sched_start=lam0, sched_end=lam0,
+                            sched_steps=1)
+            o = orc.Oracle([s], P, seed=77)
+            o.run(300)
+            s.sched_start, s.sched_end, s.sched_steps = lam0, (lam_e if d == 0 else 0.0), nst
+            orc.initial_switch_state(s)
+            o.run(nst)
+            W[d].append(s.W)
+    wf, wb = np.array(W[0]), np.array(W[1])
+    dF = orc.delta_f(wf, wb)
+    exact = orc.einstein_free_energy_difference(k, (1 - lam_e) * k, T, 63)
+    se = 0.5 * np.sqrt(wf.var(ddof=1) / nrep + wb.var(ddof=1) / nrep)
+    assert abs(dF - exact) < max(4 * se, 0.02)
+    assert abs(dF - exact) < 0.15           # 2.3 meV/atom hard bound
+    assert orc.q_diss(wf, wb) > 0.0         # second law on average
+
+
+def test_ideal_gas_npt_volume(sw_params):
+    """Ideal gas (SW off) under the isotropic barostat + Langevin: the volume
+    is Gamma distributed, V^(N_pos) exp(-P V / kB T).  The centre of mass is
+    frozen in scaled coordinates (zero momentum, box-scaled drift), so
+    N_pos = N - 1 and <V> = N kB T / P; N = 8 separates this from (N+1)
+    by 12 %."""
+    P = dict(sw_params)
+    P["epsilon"] = 0.0
+    N, T, Pg = 8, 1000.0, 0.1
+    Pe = Pg / orc.GPA_PER_EV_A3
+    Vexp = N * orc.KB * T / Pe
+    L = ((N + 1) * orc.KB * T / Pe) ** (1 / 3)
+    g = inputs.rng(960, 0, 0)
+    s = orc.OSystem(x=g.random((N, 3)) * L, v=inputs.maxwell(N, T, inputs.rng(960, 0, 1)),
+                    box=np.array([L, L, L]), mode=orc.MODE_NVT, T0=T, tau_damp=0.05,
+                    p_damp=0.1, pressure=Pg, stream=3)
+    o = orc.Oracle([s], P, seed=5)
+    o.run(2000)
+    Vs = []
+    for _ in range(30000):
+        o.step()
+        Vs.append(s.volume)
+    assert np.mean(Vs) == pytest.approx(Vexp, rel=0.05)
+
+
+# -------------------------------------------------------------- schedules ----
+def test_rs_schedule_endpoints_and_linear_temperature(sw_params):
+    """lambda(t) = 1/(1 + t/t_s (1/lambda_f - 1)): lambda(0)=1, lambda(t_s)=lambda_f
+    and the physical temperature T0/lambda is linear in t (section 4.1)."""
+    s = orc.OSystem(x=np.zeros((2, 3)), v=np.zeros((2, 3)), box=np.ones(3) * 10,
+                    mode=orc.MODE_RS, sched_start=1.0, sched_end=0.25, sched_steps=100)
+    lams = np.array([orc._lam_rs(s, k) for k in range(101)])
+    assert lams[0] == 1.0 and lams[-1] == pytest.approx(0.25, rel=1e-15)
+    T = 400.0 / lams
+    assert np.allclose(np.diff(T), (1600.0 - 400.0) / 100, rtol=1e-12)
+
+
+class _Fake:
+    def __init__(self, n, U, V, mode, T0=1000.0, start=0.0, end=0.0, steps=10):
+        self.n, self.U_int, self._V = n, U, V
+        self.mode, self.T0 = mode, T0
+        self.sched_start, self.sched_end, self.sched_steps = start, end, steps
+        self.lam, self.Ps = 1.0, 0.0
+
+    @property
+    def volume(self):
+        return self._V
+
+
+def test_dcci_temperature_control_constant_ratio_closed_form():
+    """With constant per-atom differences du, dv the discrete rule of eq.
+    Ps_coex_discreted is exact: P_S(lambda) = P0 - (lambda - 1) du/dv, so the
+    physical curve is P(T) = (T/T0) P0 - (1 - T/T0) du/dv."""
+    T0, T1, nst = 400.0, 1250.0, 50
+    I = _Fake(4096, -4.30 * 4096, 20.0 * 4096, orc.MODE_DCCI_T, T0, T0, T1, nst)
+    II = _Fake(8000, -4.10 * 8000, 17.3 * 8000, orc.MODE_DCCI_T, T0, T0, T1, nst)
+    P0 = 13.17346 / orc.GPA_PER_EV_A3
+    I.Ps = II.Ps = P0
+    du, dv = -0.20, 2.7
+    for k in range(nst):
+        lam, Ps, bad = orc.dcci_update(I, II, k)
+        assert not bad
+        I.lam = II.lam = lam
+        I.Ps = II.Ps = Ps
+    T = T0 / I.lam
+    assert T == pytest.approx(T1, rel=1e-14)
+    expect = orc.dcci_curve_const_ratio(T, T0, P0, du / dv)
+    assert I.Ps / I.lam == pytest.approx(expect, rel=1e-12)
+
+
+def test_dcci_pressure_control_inverts_lambda_rule():
+    """Eq. l_coex_discreted is the inverse of eq. Ps_coex_discreted: feeding
+    its lambda_{k+1} back into the P_S rule must reproduce P_S = lambda P at
+    every step."""
+    nst = 40
+    I = _Fake(4096, -4.30 * 4096, 20.0 * 4096, orc.MODE_DCCI_P, 400.0, 0.0, 10.2, nst)
+    II = _Fake(8000, -4.35 * 8000, 19.0 * 8000, orc.MODE_DCCI_P, 400.0, 0.0, 10.2, nst)
+    du = I.U_int / I.n - II.U_int / II.n
+    dv = I.volume / I.n - II.volume / II.n
+    for k in range(nst):
+        lam, Ps, bad = orc.dcci_update(I, II, k)
+        assert not bad
+        Ps_rule = I.Ps - (lam - I.lam) * du / dv
+        assert Ps_rule == pytest.approx(Ps, rel=1e-12, abs=1e-15)
+        P_next = (10.2 * (k + 1) / nst) / orc.GPA_PER_EV_A3
+        assert Ps / lam == pytest.approx(P_next, rel=1e-12, abs=1e-15)
+        I.lam = II.lam = lam
+        I.Ps = II.Ps = Ps
+
+
+def test_dcci_singular_guard():
+    I = _Fake(10, -43.0, 200.0, orc.MODE_DCCI_P, 400.0, 0.0, 10.0, 10)
+    II = _Fake(10, -42.0, 200.0, orc.MODE_DCCI_P, 400.0, 0.0, 10.0, 10)
+    lam, Ps, bad = orc.dcci_update(I, II, 0)
+    assert bad and lam == I.lam and Ps == I.Ps
+
+
+def test_work_is_sum_of_switch_increments(sw_params):
+    """For Frenkel-Ladd the accumulated work equals sum_k (lambda_{k+1} -
+    lambda_k)(U_int - U_ref) at the switch points (eq. Wdyn discretised)."""
+    s = _c1_system(mode=orc.MODE_FL, k_spring=5.0, T0=1000.0, tau_damp=0.1,
+                   sched_start=1.0, sched_end=0.0, sched_steps=50)
+    o = orc.Oracle([s], sw_params, seed=9)
+    acc = 0.0
+    for k in range(50):
+        du = s.U_int - s.U_ref
+        lam0 = s.lam
+        o.step()
+        acc += (s.lam - lam0) * du
+    assert s.W == pytest.approx(acc, rel=1e-13)
+    assert s.lam == 0.0
+
+
+def test_gibbs_rs_identity_at_lambda_one():
+    assert orc.gibbs_rs(-4.0, 1.0, 100, 400.0, 0.3, 0.3) == pytest.approx(-4.0)
