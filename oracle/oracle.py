@@ -441,14 +441,14 @@ class Oracle:
             za = s.veps * 0.5 * dt
             grow = np.exp(za)
             psi = 1.0 if za == 0.0 else np.expm1(za) / za
-            acc = MVV2E ** -1 / MASS_SI
+            acc = 1.0 / MVV2E / MASS_SI
             # 3. B
             s.v = s.v * decay + 0.5 * dt * acc * self.total_force(s, s.lam) * phi
             # 4. A
             s.x = s.x * grow + s.v * (0.5 * dt) * psi
             s.box = s.box * grow
             # 5. O
-            if s.tau_damp > 0.0 and s.T0 > 0.0:
+            if s.mode != MODE_NVE and s.tau_damp > 0.0 and s.T0 > 0.0:
                 c1 = np.exp(-dt / s.tau_damp)
                 c2 = np.sqrt(1.0 - c1 * c1)
                 sv = np.sqrt(KB * s.T0 / (MASS_SI * MVV2E))
