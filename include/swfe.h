@@ -1,0 +1,225 @@
+/*
+ * swfe.h -- C-ABI of libswfe, the MI355X (gfx950) library for switched-
+ * Hamiltonian molecular dynamics of silicon described by the Stillinger-Weber
+ * potential.
+ *
+ * The library implements the per-step hot path of non-equilibrium free-energy
+ * runs and dynamic Clausius-Clapeyron integration (dCCI):
+ *   - cell-list neighbour build,
+ *   - Stillinger-Weber energy, force, virial and parameter gradient,
+ *   - velocity Verlet with a Langevin thermostat and an isotropic barostat,
+ *   - the lambda-switched Hamiltonian and its dH/dlambda work integral for
+ *     Frenkel-Ladd, reversible-scaling, pressure-switching and coupled-phase
+ *     dCCI runs.
+ * Passages of the paper are cited as section / equation labels of
+ * "Non-equilibrium free-energy calculation of phase-boundaries using LAMMPS"
+ * (Cajahuaringa and Antonelli).
+ *
+ * Conventions shared by every call
+ *   - Every function returns int: SWFE_OK (0) or a negative SWFE_E_* code;
+ *     swfe_last_error() gives a message.  Errors are per context.
+ *   - The caller owns all device memory (positions, velocities, forces,
+ *     anchors, workspace) and passes raw device pointers.  The library owns
+ *     only the opaque context and its host-side tables.
+ *   - Work is enqueued on the caller's HIP stream (passed as void*; NULL is the
+ *     default stream).  Only calls that return host data synchronise.
+ *   - Units: eV, Angstrom, ps, amu, K; pressures at the ABI in GPa.
+ *   - Atom arrays are structure-of-arrays over all systems concatenated:
+ *     component c (0,1,2 = x,y,z) of global atom i is at [c * n_total + i];
+ *     system s owns atoms [offset_s, offset_s + n_s).
+ */
+#ifndef SWFE_H
+#define SWFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct swfe_ctx swfe_ctx;
+
+/* ---- status codes ------------------------------------------------------ */
+#define SWFE_OK 0
+#define SWFE_E_INVALID_ARG -1   /* bad pointer, size, mode or parameter */
+#define SWFE_E_BOX_TOO_SMALL -2 /* a box length below twice the cutoff */
+#define SWFE_E_OVERFLOW -3      /* neighbour list (32 per atom) overflowed */
+#define SWFE_E_NONFINITE -4     /* NaN/Inf in an energy, force or position */
+#define SWFE_E_DCCI_SINGULAR -5 /* dCCI denominator or lambda out of range */
+#define SWFE_E_HIP -6           /* a HIP runtime call failed */
+#define SWFE_E_STATE -7         /* call out of order (e.g. before init) */
+#define SWFE_E_NOMEM -8         /* workspace too small */
+
+/* ---- modes (one per system) --------------------------------------------
+ * FORCE   no dynamics; forces only
+ * NVE     velocity Verlet
+ * NVT     + Langevin thermostat (NPT when p_damp > 0: target P)
+ * FL      Frenkel-Ladd Hamiltonian interpolation H = lam H_int + (1-lam) H_ref,
+ *         Einstein reference, lambda linear in time (section 2.1)
+ * RS      reversible scaling H = K + lam U_int + P_S V, P_S = lam P,
+ *         1/lam linear in time (eqs. H_RS, T_sc, P_sc; section 4.1)
+ * AS_P    pressure switching, work = int dP/dt V dt (eq. Wmech_dyn)
+ * DCCI_T  dCCI with lambda (temperature) control (eq. Ps_coex_discreted)
+ * DCCI_P  dCCI with pressure control (eq. l_coex_discreted)
+ */
+#define SWFE_MODE_FORCE 0
+#define SWFE_MODE_NVE 1
+#define SWFE_MODE_NVT 2
+#define SWFE_MODE_FL 3
+#define SWFE_MODE_RS 4
+#define SWFE_MODE_AS_P 5
+#define SWFE_MODE_DCCI_T 6
+#define SWFE_MODE_DCCI_P 7
+
+/* precision of the pair and triplet term arithmetic */
+#define SWFE_PREC_FP64 0  /* everything FP64 */
+#define SWFE_PREC_MIXED 1 /* FP32 terms; FP64 positions, accumulation, work */
+
+/* compute_forces flags */
+#define SWFE_PARAM_GRAD 1u /* also dE/dtheta */
+#define SWFE_STRAIN 2u     /* evaluate at (I + strain) x, (I + strain) box */
+
+/* Stillinger-Weber parameters (Stillinger and Weber 1985, the potential the
+ * paper uses for silicon in its applications section):
+ *   phi2(r) = epsilon A [B (sigma/r)^p - (sigma/r)^q] exp(sigma / (r - a sigma))
+ *   phi3    = lambda_sw epsilon (cos theta_jik - cos0)^2 g(r_ij) g(r_ik),
+ *   g(r)    = exp(gamma sigma / (r - a sigma)); both vanish for r >= a sigma.
+ * mass in amu. */
+typedef struct {
+    double A, B, p, q, a, lambda_sw, gamma, sigma, epsilon, cos0, mass;
+} swfe_sw_params;
+
+/* One periodic orthorhombic system. */
+typedef struct {
+    int64_t n_atoms;
+    int64_t offset;   /* first global atom index of this system */
+    double box[3];    /* box lengths (A); each must be >= 2 a sigma */
+    int32_t mode;     /* SWFE_MODE_* */
+    int32_t partner;  /* dCCI: index of the coupled system, else -1 */
+    double k_spring;  /* Einstein spring constant (eV/A^2), FL only */
+    double T0;        /* thermostat temperature (K); 0 disables the O step */
+    double tau_damp;  /* Langevin damping time (ps); 0 disables the O step */
+    double p_damp;    /* barostat period (ps); 0 keeps the box fixed */
+    double pressure;  /* physical pressure P (GPa) for NPT, RS, dCCI-T */
+    uint64_t stream;  /* noise stream id: Philox key word 1 */
+    /* schedule: start/end of the controlled variable and its length in steps
+     * FL: lambda; RS: lambda (1/lambda is ramped); AS_P, DCCI_P: P in GPa;
+     * DCCI_T: T in K.  sched_steps = 0 holds the start value. */
+    double sched_start, sched_end;
+    int64_t sched_steps;
+} swfe_system_desc;
+
+/* Device buffers, all caller owned. */
+typedef struct {
+    double *x;          /* [3][n_total] positions (unwrapped), A */
+    double *v;          /* [3][n_total] velocities, A/ps */
+    double *f;          /* [3][n_total] out: interaction force F_int (unscaled) */
+    const double *x0;   /* [3][n_total] Einstein anchors; may be NULL if no FL */
+    double *e_atom;     /* [n_total] out: per-atom energy; may be NULL */
+    void *workspace;    /* scratch of swfe_workspace_bytes() bytes */
+    size_t workspace_bytes;
+} swfe_buffers;
+
+/* Host copy of one system's switching state. */
+typedef struct {
+    double lam;        /* coupling parameter lambda */
+    double Ps;         /* barostat target (scaled pressure P_S), GPa */
+    double W;          /* accumulated work, eV */
+    double U_int;      /* unscaled interaction energy at the current positions */
+    double U_ref;      /* Einstein energy (FL) */
+    double K;          /* kinetic energy, eV */
+    double V;          /* volume, A^3 */
+    double virial[9];  /* dU_int/dstrain (eV), row-major */
+    double box[3];
+    double veps;       /* barostat rate (1/ps) */
+    double T_inst;     /* kinetic temperature over 3N-3 degrees of freedom */
+    int64_t step;      /* steps taken since init (noise counter) */
+    int64_t sched_k;   /* steps taken on the current schedule */
+    int32_t err;       /* sticky device error bits of this system */
+    int32_t pad;
+} swfe_system_state;
+
+/* Per-system row written by swfe_compute_forces when out != NULL. */
+#define SWFE_OUT_STRIDE 20 /* [E, U_ref, dE/dstrain (9), dE/dtheta (9)] */
+
+/* ---- context -------------------------------------------------------------
+ * swfe_create: allocate an empty context.  swfe_destroy: free it (also
+ * releases captured graphs); NULL is ignored. */
+int swfe_create(swfe_ctx **out);
+void swfe_destroy(swfe_ctx *ctx);
+const char *swfe_last_error(const swfe_ctx *ctx);
+
+/* Bytes of device workspace needed for these systems.  Checks descriptors
+ * (SWFE_E_INVALID_ARG, SWFE_E_BOX_TOO_SMALL) without touching the GPU. */
+int swfe_workspace_bytes(const swfe_system_desc *d, int32_t n_sys, const swfe_sw_params *p,
+                         size_t *bytes);
+
+/* Set up n_sys systems on the caller's buffers (host descriptors, device
+ * buffers), then evaluate the initial interaction.  seed is Philox key word
+ * 0 of the thermostat noise; dt in ps; precision SWFE_PREC_*.  Each system's
+ * schedule starts at step 0 (lambda, P_S from sched_start).  Velocities must
+ * carry zero total momentum per system for the fixed centre of mass the
+ * zero-sum noise maintains.  Synchronises the stream once. */
+int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys,
+                     const swfe_sw_params *p, const swfe_buffers *b, uint64_t seed, double dt,
+                     int32_t precision, void *stream);
+
+/* Cell binning of the current positions (step a1): cell index per atom,
+ * deterministic counting sort by cell (ties in atom order). */
+int swfe_build_neighbors(swfe_ctx *ctx, void *stream);
+
+/* Interaction at the current positions: binning, pair terms and three-body
+ * moments, force gather, per-system reductions.  Writes f (and e_atom).
+ * flags: SWFE_PARAM_GRAD, SWFE_STRAIN.  strain: host [n_sys][9] diagonal
+ * strains (off-diagonal entries must be 0) used with SWFE_STRAIN, else NULL.
+ * grad_scale: device [n_sys] upstream gradient dL/dE or NULL (=1).
+ * grad_x: device [3][n_total] out, dL/dx = -F grad_scale, or NULL.
+ * out: device [n_sys][SWFE_OUT_STRIDE] (E, U_ref, dE/dstrain * gs,
+ * dE/dtheta * gs with theta = A,B,p,q,a,lambda_sw,gamma,sigma,epsilon), or
+ * NULL.  Does not synchronise. */
+int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain,
+                        const double *grad_scale, double *grad_x, double *out, void *stream);
+
+/* Install new schedules (sched_start/sched_end/sched_steps of the given
+ * descriptors; NULL keeps the current ones) and reset the schedule step and
+ * work accumulators of every system.  Does not synchronise. */
+int swfe_set_schedule(swfe_ctx *ctx, const swfe_system_desc *d, void *stream);
+
+/* Advance every system by n_steps of switched dynamics (steps a4-a9):
+ * switch lambda and accumulate work, barostat half step, B A O A kick/drift/
+ * Langevin, interaction, B, barostat half step.  dCCI pairs update their
+ * shared lambda and P_S from both phases' instantaneous per-atom energy and
+ * volume.  use_graph != 0 replays one captured step graph.  Errors raised
+ * on the device (overflow, non-finite, dCCI singular, box too small) are
+ * reported by the next synchronising call. */
+int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *stream);
+
+/* Synchronise and copy per-system work W (eV), lambda, P_S (GPa) and the
+ * schedule step to host arrays of n_sys entries (any may be NULL).  Returns
+ * the first pending device error as a status code. */
+int swfe_work_integral(swfe_ctx *ctx, double *W, double *lam, double *Ps, int64_t *steps,
+                       void *stream);
+
+/* Synchronise and copy the full state of every system. */
+int swfe_get_state(swfe_ctx *ctx, swfe_system_state *out, void *stream);
+
+/* Copy of the log ring: every log_every steps one row per system of
+ * (step, lambda, P_S GPa, P GPa, T K, U_int/N, V/N, W).  swfe_set_log sets
+ * log_every (0 disables) and the ring capacity in rows. */
+#define SWFE_LOG_STRIDE 8
+int swfe_set_log(swfe_ctx *ctx, int32_t log_every, int32_t capacity);
+int swfe_read_log(swfe_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows, void *stream);
+
+/* Tuning: block size for the force passes (64, 128 or 256; 0 = autotune by
+ * timing compute_forces on the installed systems). */
+int swfe_set_block(swfe_ctx *ctx, int32_t block, void *stream);
+int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream);
+
+/* Sizes needed by the caller: total atoms and systems of the context. */
+int swfe_sizes(const swfe_ctx *ctx, int64_t *n_total, int32_t *n_sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWFE_H */

@@ -1,0 +1,715 @@
+// swfe_api.hip -- host runtime behind the C-ABI declared in include/swfe.h.
+//
+// Holds the per-context tables (system descriptors, tile list, workspace
+// carve-up), validates inputs, enqueues the kernels of swfe_kernels.hip on
+// the caller's stream and, on request, captures one dynamics step into a HIP
+// graph that is replayed for every step.
+#include "../../include/swfe.h"
+#include "swfe_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace swfe;
+
+namespace {
+
+// CODATA 2018 constants (metal units), defined here for the library.
+constexpr double kKB = 8.617333262e-5;                                  // eV/K
+constexpr double kMvv2e = 1.66053906660e-27 * 1e-20 / 1e-24 / 1.602176634e-19;  // eV/(amu A^2/ps^2)
+constexpr double kGpa = 1.602176634e-19 / 1e-30 / 1e9;                  // GPa per eV/A^3
+constexpr int kLogCapMax = 16384;                                       // rows of the log ring
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+__global__ void k_set_ctr(int64_t *ctr, int64_t value) { ctr[0] = value; }
+
+__global__ void k_clear_err(SysState *st, int n_sys)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_sys) st[s].err = 0;
+}
+
+struct Plan {
+    std::vector<SysDesc> desc;
+    int64_t n_total = 0;
+    int64_t cells = 0;       // sum of per-system cell capacities
+    int64_t max_tiles = 0;   // tiles at the smallest block size
+    Layout lay{};
+};
+
+}  // namespace
+
+struct swfe_ctx {
+    std::string err;
+    bool ready = false;
+    int n_sys = 0;
+    int64_t n_total = 0;
+    std::vector<swfe_system_desc> hdesc;
+    swfe_sw_params hsw{};
+    Plan plan;
+    std::vector<Tile> tiles;
+    SwParams sw{};
+    int mixed = 0;
+    double dt = 0.001;
+    uint64_t seed = 0;
+    int block = 256;
+    swfe_buffers buf{};
+    DevPtrs ptrs{};
+    int log_every = 0, log_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+    hipStream_t cap_stream = nullptr;  // library-owned stream used only for capture
+};
+
+namespace {
+
+int fail(swfe_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ctx, SWFE_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_dcci(int m) { return m == SWFE_MODE_DCCI_T || m == SWFE_MODE_DCCI_P; }
+
+SwParams make_sw(const swfe_sw_params &p)
+{
+    SwParams s{};
+    s.A = p.A;
+    s.B = p.B;
+    s.p = p.p;
+    s.q = p.q;
+    s.a = p.a;
+    s.lam = p.lambda_sw;
+    s.gam = p.gamma;
+    s.sig = p.sigma;
+    s.eps = p.epsilon;
+    s.cos0 = p.cos0;
+    s.rc = p.a * p.sigma;
+    s.rc2 = s.rc * s.rc;
+    s.eA = p.epsilon * p.A;
+    s.le = p.lambda_sw * p.epsilon;
+    auto integral = [](double e) { return (e >= 0 && e <= 16 && e == std::floor(e)) ? (int)e : -1; };
+    s.ip = integral(p.p);
+    s.iq = integral(p.q);
+    return s;
+}
+
+// Validate descriptors and compute the per-system device descriptors and the
+// workspace layout.  Does not touch the GPU.
+int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw_params *p,
+                 double dt, Plan &out)
+{
+    if (!d || !p || n_sys <= 0) return fail(ctx, SWFE_E_INVALID_ARG, "null descriptor/params or n_sys <= 0");
+    if (!(p->a > 0 && p->sigma > 0 && p->mass > 0))
+        return fail(ctx, SWFE_E_INVALID_ARG, "SW parameters need a > 0, sigma > 0, mass > 0");
+    if (!(dt > 0)) return fail(ctx, SWFE_E_INVALID_ARG, "dt must be > 0");
+    const double rc = p->a * p->sigma;
+    Plan P;
+    int64_t off = 0;
+    int64_t tiles = 0, cells = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        const swfe_system_desc &q = d[s];
+        char msg[256];
+        if (q.n_atoms < 2 || q.n_atoms > (1 << 30)) {
+            snprintf(msg, sizeof msg, "system %d: n_atoms must be in [2, 2^30]", s);
+            return fail(ctx, SWFE_E_INVALID_ARG, msg);
+        }
+        if (q.offset != off) {
+            snprintf(msg, sizeof msg, "system %d: offset must be %lld (systems are contiguous)", s,
+                     (long long)off);
+            return fail(ctx, SWFE_E_INVALID_ARG, msg);
+        }
+        for (int k = 0; k < 3; ++k)
+            if (!(q.box[k] >= 2.0 * rc)) {
+                snprintf(msg, sizeof msg, "system %d: box length %g below twice the cutoff %g", s,
+                         q.box[k], 2.0 * rc);
+                return fail(ctx, SWFE_E_BOX_TOO_SMALL, msg);
+            }
+        if (q.mode < 0 || q.mode > 7) return fail(ctx, SWFE_E_INVALID_ARG, "unknown mode");
+        if (q.tau_damp < 0 || q.T0 < 0 || q.p_damp < 0)
+            return fail(ctx, SWFE_E_INVALID_ARG, "negative T0, tau_damp or p_damp");
+        if (q.p_damp > 0 && !(q.T0 > 0))
+            return fail(ctx, SWFE_E_INVALID_ARG, "a barostat (p_damp > 0) needs T0 > 0");
+        if (q.mode == SWFE_MODE_FL && q.p_damp > 0)
+            return fail(ctx, SWFE_E_INVALID_ARG, "Frenkel-Ladd switching runs at fixed volume");
+        if (q.mode == SWFE_MODE_RS && !(q.sched_start > 0 && q.sched_end > 0))
+            return fail(ctx, SWFE_E_INVALID_ARG, "reversible scaling needs lambda > 0");
+        if (q.mode == SWFE_MODE_DCCI_T && !(q.sched_start > 0 && q.sched_end > 0 && q.T0 > 0))
+            return fail(ctx, SWFE_E_INVALID_ARG, "dCCI-T needs positive temperatures");
+        if (is_dcci(q.mode)) {
+            if (q.partner < 0 || q.partner >= n_sys || q.partner == s)
+                return fail(ctx, SWFE_E_INVALID_ARG, "dCCI system without a valid partner");
+            const swfe_system_desc &r = d[q.partner];
+            if (r.partner != s || r.mode != q.mode || r.sched_start != q.sched_start ||
+                r.sched_end != q.sched_end || r.sched_steps != q.sched_steps || r.T0 != q.T0 ||
+                r.pressure != q.pressure)
+                return fail(ctx, SWFE_E_INVALID_ARG,
+                            "dCCI partners must point at each other and share mode, schedule, T0, P");
+        }
+        SysDesc sd{};
+        sd.off = q.offset;
+        sd.n = q.n_atoms;
+        sd.mode = q.mode;
+        sd.partner = is_dcci(q.mode) ? q.partner : -1;
+        int64_t cap = 1;
+        for (int k = 0; k < 3; ++k) {
+            int n = (int)std::floor(q.box[k] * 1.3 / rc);
+            n = std::max(1, std::min(n, 256));
+            sd.nc_max[k] = n;
+            cap *= n;
+        }
+        if (cells + cap + n_sys > (int64_t)1 << 30) return fail(ctx, SWFE_E_INVALID_ARG, "too many cells");
+        sd.cell_base = (int32_t)cells;
+        sd.cell_cap = (int32_t)cap;
+        cells += cap;
+        sd.tile_begin = sd.tile_end = 0;
+        sd.k_spring = q.k_spring;
+        sd.T0 = q.T0;
+        sd.tau_damp = q.tau_damp;
+        sd.p_damp = q.p_damp;
+        sd.pressure = q.pressure / kGpa;
+        sd.nf = 3.0 * (double)q.n_atoms - 3.0;
+        sd.alpha = 1.0 + 3.0 / sd.nf;
+        sd.wpiston = q.p_damp > 0 ? ((sd.nf + 3) * kKB) * q.T0 * (q.p_damp * q.p_damp) : 1.0;
+        sd.c1 = q.tau_damp > 0 ? std::exp(-dt / q.tau_damp) : 1.0;
+        sd.c2 = std::sqrt(1.0 - sd.c1 * sd.c1);
+        sd.sigv = std::sqrt(kKB * q.T0 / (p->mass * kMvv2e));
+        sd.acc = 1.0 / kMvv2e / p->mass;
+        sd.mvv2e_m = 0.5 * p->mass * kMvv2e;
+        sd.stream = q.stream;
+        sd.s_start = q.sched_start;
+        sd.s_end = q.sched_end;
+        sd.s_steps = q.sched_steps;
+        P.desc.push_back(sd);
+        tiles += (q.n_atoms + 63) / 64;
+        off += q.n_atoms;
+    }
+    if (off >= ((int64_t)1 << 31) / 32) return fail(ctx, SWFE_E_INVALID_ARG, "too many atoms");
+    P.n_total = off;
+    P.cells = cells;
+    P.max_tiles = tiles;
+    Layout &L = P.lay;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const size_t n = (size_t)off;
+    L.cell_of = take(4 * n);
+    L.sorted = take(4 * n);
+    L.cell_count = take(4 * (size_t)cells);
+    L.cursor = take(4 * (size_t)cells);
+    L.cell_start = take(4 * ((size_t)cells + n_sys));
+    L.nbr = take(4 * n * kMaxNb);
+    L.nnb = take(4 * n);
+    L.mom = take(8 * n * 11);
+    L.f2 = take(0);
+    L.part1 = take(8 * (size_t)tiles * kNumPart);
+    L.part2 = take(8 * (size_t)tiles * kNumPart);
+    L.desc = take(sizeof(SysDesc) * n_sys);
+    L.state = take(sizeof(SysState) * n_sys);
+    L.tiles = take(sizeof(Tile) * (size_t)tiles);
+    L.log = take(8 * (size_t)kLogCapMax * SWFE_LOG_STRIDE);
+    L.misc = take(8 * 4 + 8 * 9 * (size_t)n_sys);
+    L.total = o;
+    out = std::move(P);
+    return SWFE_OK;
+}
+
+void build_tiles(swfe_ctx *c)
+{
+    c->tiles.clear();
+    for (int s = 0; s < c->n_sys; ++s) {
+        SysDesc &d = c->plan.desc[s];
+        d.tile_begin = (int32_t)c->tiles.size();
+        for (int64_t a = 0; a < d.n; a += c->block) {
+            Tile t{};
+            t.sys = s;
+            t.start = (int32_t)(d.off + a);
+            t.count = (int32_t)std::min<int64_t>(c->block, d.n - a);
+            c->tiles.push_back(t);
+        }
+        d.tile_end = (int32_t)c->tiles.size();
+    }
+}
+
+Ctl make_ctl(const swfe_ctx *c, int in_step, int flags)
+{
+    Ctl k{};
+    k.n_total = c->n_total;
+    k.n_sys = c->n_sys;
+    k.n_tiles = (int32_t)c->tiles.size();
+    k.dt = c->dt;
+    k.seed = c->seed;
+    k.flags = flags;
+    k.in_step = in_step;
+    return k;
+}
+
+void drop_graph(swfe_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_valid = false;
+}
+
+int upload_tables(swfe_ctx *c, hipStream_t s)
+{
+    HIPCHK(c, hipMemcpyAsync((void *)c->ptrs.desc, c->plan.desc.data(), sizeof(SysDesc) * c->n_sys,
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync((void *)c->ptrs.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return SWFE_OK;
+}
+
+int enqueue_forces(swfe_ctx *c, const DevPtrs &p, int flags, hipStream_t s)
+{
+    Ctl k = make_ctl(c, 0, flags);
+    HIPCHK(c, launch_assign_cells(k, p, c->sw, c->block, s));
+    HIPCHK(c, launch_bin(k, p, c->sw, s));
+    HIPCHK(c, launch_pass1(k, p, c->sw, c->mixed, c->block, s));
+    HIPCHK(c, launch_pass2(k, p, c->sw, c->mixed, c->block, s));
+    HIPCHK(c, launch_finalize(k, p, c->sw, 0, c->log_every, c->log_cap, s));
+    return SWFE_OK;
+}
+
+int enqueue_step(swfe_ctx *c, hipStream_t s)
+{
+    Ctl k = make_ctl(c, 1, 0);
+    HIPCHK(c, launch_integrate(k, c->ptrs, c->sw, c->block, s));
+    HIPCHK(c, launch_bin(k, c->ptrs, c->sw, s));
+    HIPCHK(c, launch_pass1(k, c->ptrs, c->sw, c->mixed, c->block, s));
+    HIPCHK(c, launch_pass2(k, c->ptrs, c->sw, c->mixed, c->block, s));
+    HIPCHK(c, launch_finalize(k, c->ptrs, c->sw, 1, c->log_every, c->log_cap, s));
+    return SWFE_OK;
+}
+
+int read_states(swfe_ctx *c, std::vector<SysState> &st, hipStream_t s)
+{
+    st.resize(c->n_sys);
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipMemcpy(st.data(), c->ptrs.state, sizeof(SysState) * c->n_sys, hipMemcpyDeviceToHost));
+    return SWFE_OK;
+}
+
+// First pending device error as a status code; clears the device bits.
+int take_device_error(swfe_ctx *c, const std::vector<SysState> &st, hipStream_t s)
+{
+    int bits = 0, who = -1;
+    for (int i = 0; i < c->n_sys; ++i)
+        if (st[i].err && who < 0) {
+            bits = st[i].err;
+            who = i;
+        }
+    if (!bits) return SWFE_OK;
+    hipLaunchKernelGGL(k_clear_err, dim3((c->n_sys + 63) / 64), dim3(64), 0, s, c->ptrs.state, c->n_sys);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(s));
+    char msg[160];
+    const char *what = (bits & ERR_NONFINITE) ? "non-finite value"
+                       : (bits & ERR_OVERFLOW) ? "neighbour list overflow (more than 32 within the cutoff)"
+                       : (bits & ERR_BOX) ? "box length fell below twice the cutoff"
+                                          : "dCCI update singular (|dv| or denominator too small, or lambda out of (0.05, 20))";
+    snprintf(msg, sizeof msg, "system %d: %s", who, what);
+    int code = (bits & ERR_NONFINITE) ? SWFE_E_NONFINITE
+               : (bits & ERR_OVERFLOW) ? SWFE_E_OVERFLOW
+               : (bits & ERR_BOX) ? SWFE_E_BOX_TOO_SMALL
+                                  : SWFE_E_DCCI_SINGULAR;
+    return fail(c, code, msg);
+}
+
+}  // namespace
+
+extern "C" {
+
+int swfe_create(swfe_ctx **out)
+{
+    if (!out) return SWFE_E_INVALID_ARG;
+    *out = new swfe_ctx();
+    return SWFE_OK;
+}
+
+void swfe_destroy(swfe_ctx *ctx)
+{
+    if (!ctx) return;
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+}
+
+const char *swfe_last_error(const swfe_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int swfe_workspace_bytes(const swfe_system_desc *d, int32_t n_sys, const swfe_sw_params *p, size_t *bytes)
+{
+    if (!bytes) return SWFE_E_INVALID_ARG;
+    Plan P;
+    int rc = plan_systems(nullptr, d, n_sys, p, 0.001, P);
+    if (rc) return rc;
+    *bytes = P.lay.total;
+    return SWFE_OK;
+}
+
+int swfe_sizes(const swfe_ctx *ctx, int64_t *n_total, int32_t *n_sys)
+{
+    if (!ctx || !ctx->ready) return SWFE_E_STATE;
+    if (n_total) *n_total = ctx->n_total;
+    if (n_sys) *n_sys = ctx->n_sys;
+    return SWFE_OK;
+}
+
+int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, const swfe_sw_params *p,
+                     const swfe_buffers *b, uint64_t seed, double dt, int32_t precision, void *stream)
+{
+    if (!ctx) return SWFE_E_INVALID_ARG;
+    ctx->ready = false;
+    drop_graph(ctx);
+    if (!b || !b->x || !b->v || !b->f || !b->workspace)
+        return fail(ctx, SWFE_E_INVALID_ARG, "buffers x, v, f and workspace are required");
+    if (precision != SWFE_PREC_FP64 && precision != SWFE_PREC_MIXED)
+        return fail(ctx, SWFE_E_INVALID_ARG, "precision must be SWFE_PREC_FP64 or SWFE_PREC_MIXED");
+    Plan P;
+    int rc = plan_systems(ctx, d, n_sys, p, dt, P);
+    if (rc) return rc;
+    for (int s = 0; s < n_sys; ++s)
+        if (d[s].mode == SWFE_MODE_FL && !b->x0)
+            return fail(ctx, SWFE_E_INVALID_ARG, "Frenkel-Ladd systems need Einstein anchors x0");
+    if (b->workspace_bytes < P.lay.total) {
+        char msg[128];
+        snprintf(msg, sizeof msg, "workspace too small: %zu < %zu bytes", b->workspace_bytes, P.lay.total);
+        return fail(ctx, SWFE_E_NOMEM, msg);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ctx->plan = std::move(P);
+    ctx->n_sys = n_sys;
+    ctx->n_total = ctx->plan.n_total;
+    ctx->hdesc.assign(d, d + n_sys);
+    ctx->hsw = *p;
+    ctx->sw = make_sw(*p);
+    ctx->mixed = precision == SWFE_PREC_MIXED;
+    ctx->dt = dt;
+    ctx->seed = seed;
+    ctx->buf = *b;
+    if (ctx->block != 64 && ctx->block != 128 && ctx->block != 256) ctx->block = 256;
+    build_tiles(ctx);
+
+    char *w = (char *)b->workspace;
+    const Layout &L = ctx->plan.lay;
+    DevPtrs &q = ctx->ptrs;
+    q = DevPtrs{};
+    q.x = b->x;
+    q.v = b->v;
+    q.f = b->f;
+    q.x0 = b->x0;
+    q.e_atom = b->e_atom;
+    q.cell_of = (int32_t *)(w + L.cell_of);
+    q.sorted = (int32_t *)(w + L.sorted);
+    q.cell_count = (int32_t *)(w + L.cell_count);
+    q.cursor = (int32_t *)(w + L.cursor);
+    q.cell_start = (int32_t *)(w + L.cell_start);
+    q.nbr = (int32_t *)(w + L.nbr);
+    q.nnb = (int32_t *)(w + L.nnb);
+    q.mom = (double *)(w + L.mom);
+    q.f2 = nullptr;
+    q.part1 = (double *)(w + L.part1);
+    q.part2 = (double *)(w + L.part2);
+    q.desc = (const SysDesc *)(w + L.desc);
+    q.state = (SysState *)(w + L.state);
+    q.tiles = (const Tile *)(w + L.tiles);
+    q.log = (double *)(w + L.log);
+    q.ctr = (int64_t *)(w + L.misc);
+    q.misc = nullptr;
+
+    std::vector<SysState> st(n_sys);
+    for (int i = 0; i < n_sys; ++i) {
+        SysState &x = st[i];
+        memset(&x, 0, sizeof x);
+        for (int k = 0; k < 3; ++k) {
+            x.box[k] = d[i].box[k];
+            x.pscale[k] = 1.0;
+        }
+        x.decay = x.phi = x.grow = x.psi = 1.0;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(q.state, st.data(), sizeof(SysState) * n_sys, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemsetAsync(w + L.misc, 0, 32, s));
+    rc = upload_tables(ctx, s);
+    if (rc) return rc;
+    Ctl k = make_ctl(ctx, 0, 0);
+    HIPCHK(ctx, launch_reset_schedule(k, q, s));
+    rc = enqueue_forces(ctx, q, 0, s);
+    if (rc) return rc;
+    std::vector<SysState> now;
+    rc = read_states(ctx, now, s);
+    if (rc) return rc;
+    rc = take_device_error(ctx, now, s);
+    if (rc) return rc;
+    ctx->ready = true;
+    return SWFE_OK;
+}
+
+int swfe_build_neighbors(swfe_ctx *ctx, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    Ctl k = make_ctl(ctx, 0, 0);
+    HIPCHK(ctx, launch_assign_cells(k, ctx->ptrs, ctx->sw, ctx->block, s));
+    HIPCHK(ctx, launch_bin(k, ctx->ptrs, ctx->sw, s));
+    return SWFE_OK;
+}
+
+int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain, const double *grad_scale,
+                        double *grad_x, double *out, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (flags & ~(SWFE_PARAM_GRAD | SWFE_STRAIN)) return fail(ctx, SWFE_E_INVALID_ARG, "unknown flags");
+    hipStream_t s = (hipStream_t)stream;
+    DevPtrs p = ctx->ptrs;
+    p.grad_scale = grad_scale;
+    p.grad_x = grad_x;
+    p.out = out;
+    Ctl k = make_ctl(ctx, 0, (int)flags);
+    double *diag = (double *)((char *)ctx->buf.workspace + ctx->plan.lay.misc + 32);
+    if (flags & SWFE_STRAIN) {
+        if (!strain) return fail(ctx, SWFE_E_INVALID_ARG, "SWFE_STRAIN needs a strain array");
+        std::vector<double> dg(3 * ctx->n_sys);
+        for (int i = 0; i < ctx->n_sys; ++i) {
+            for (int a = 0; a < 3; ++a)
+                for (int b2 = 0; b2 < 3; ++b2)
+                    if (a != b2 && strain[9 * i + 3 * a + b2] != 0.0)
+                        return fail(ctx, SWFE_E_INVALID_ARG, "only diagonal strains keep the box orthorhombic");
+            for (int a = 0; a < 3; ++a) {
+                dg[3 * i + a] = strain[9 * i + 4 * a];
+                if (!(1.0 + dg[3 * i + a] > 0.5)) return fail(ctx, SWFE_E_INVALID_ARG, "strain too large");
+            }
+        }
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        HIPCHK(ctx, hipMemcpy(diag, dg.data(), sizeof(double) * dg.size(), hipMemcpyHostToDevice));
+        HIPCHK(ctx, launch_set_pscale(k, p, diag, s));
+    }
+    int rc = enqueue_forces(ctx, p, (int)flags, s);
+    if (rc) return rc;
+    if (flags & SWFE_STRAIN) HIPCHK(ctx, launch_set_pscale(k, p, nullptr, s));
+    return SWFE_OK;
+}
+
+int swfe_set_schedule(swfe_ctx *ctx, const swfe_system_desc *d, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    if (d) {
+        for (int i = 0; i < ctx->n_sys; ++i) {
+            swfe_system_desc q = ctx->hdesc[i];
+            q.sched_start = d[i].sched_start;
+            q.sched_end = d[i].sched_end;
+            q.sched_steps = d[i].sched_steps;
+            ctx->hdesc[i] = q;
+        }
+        Plan P;
+        int rc = plan_systems(ctx, ctx->hdesc.data(), ctx->n_sys, &ctx->hsw, ctx->dt, P);
+        if (rc) return rc;
+        for (int i = 0; i < ctx->n_sys; ++i) {
+            ctx->plan.desc[i].s_start = d[i].sched_start;
+            ctx->plan.desc[i].s_end = d[i].sched_end;
+            ctx->plan.desc[i].s_steps = d[i].sched_steps;
+        }
+        int r2 = upload_tables(ctx, s);
+        if (r2) return r2;
+    }
+    Ctl k = make_ctl(ctx, 0, 0);
+    HIPCHK(ctx, launch_reset_schedule(k, ctx->ptrs, s));
+    return SWFE_OK;
+}
+
+int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (n_steps < 0) return fail(ctx, SWFE_E_INVALID_ARG, "n_steps < 0");
+    if (n_steps == 0) return SWFE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, s, ctx->ptrs.ctr, (int64_t)n_steps);
+    HIPCHK(ctx, hipGetLastError());
+    Ctl k = make_ctl(ctx, 1, 0);
+    HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, 2, ctx->log_every, ctx->log_cap, s));
+    if (!use_graph) {
+        for (int64_t i = 0; i < n_steps; ++i) {
+            int rc = enqueue_step(ctx, s);
+            if (rc) return rc;
+        }
+        return SWFE_OK;
+    }
+    if (!ctx->graph_valid) {
+        // Capture one step on a library-owned stream (the caller's stream may
+        // be the legacy default stream, which cannot be captured); the graph
+        // is then launched on the caller's stream.
+        drop_graph(ctx);
+        if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(ctx, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIPCHK(ctx, e);
+        ctx->graph = g;
+        HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+        ctx->graph_valid = true;
+    }
+    for (int64_t i = 0; i < n_steps; ++i) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));
+    return SWFE_OK;
+}
+
+int swfe_get_state(swfe_ctx *ctx, swfe_system_state *out, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!out) return fail(ctx, SWFE_E_INVALID_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<SysState> st;
+    int rc = read_states(ctx, st, s);
+    if (rc) return rc;
+    for (int i = 0; i < ctx->n_sys; ++i) {
+        swfe_system_state &o = out[i];
+        const SysState &x = st[i];
+        const SysDesc &d = ctx->plan.desc[i];
+        o.lam = x.lam;
+        o.Ps = x.Ps * kGpa;
+        o.W = x.W;
+        o.U_int = x.U_int;
+        o.U_ref = x.U_ref;
+        o.K = x.K;
+        o.V = x.box[0] * x.box[1] * x.box[2];
+        for (int k = 0; k < 9; ++k) o.virial[k] = x.vir[k];
+        for (int k = 0; k < 3; ++k) o.box[k] = x.box[k];
+        o.veps = x.veps;
+        o.T_inst = 2.0 * x.K / (d.nf * kKB);
+        o.step = x.step;
+        o.sched_k = x.k;
+        o.err = x.err;
+        o.pad = 0;
+    }
+    return take_device_error(ctx, st, s);
+}
+
+int swfe_work_integral(swfe_ctx *ctx, double *W, double *lam, double *Ps, int64_t *steps, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<SysState> st;
+    int rc = read_states(ctx, st, s);
+    if (rc) return rc;
+    for (int i = 0; i < ctx->n_sys; ++i) {
+        if (W) W[i] = st[i].W;
+        if (lam) lam[i] = st[i].lam;
+        if (Ps) Ps[i] = st[i].Ps * kGpa;
+        if (steps) steps[i] = st[i].k;
+    }
+    return take_device_error(ctx, st, s);
+}
+
+int swfe_set_log(swfe_ctx *ctx, int32_t log_every, int32_t capacity)
+{
+    if (!ctx) return SWFE_E_INVALID_ARG;
+    if (log_every < 0 || capacity < 0 || capacity > kLogCapMax)
+        return fail(ctx, SWFE_E_INVALID_ARG, "log_every >= 0 and 0 <= capacity <= 16384 required");
+    ctx->log_every = log_every;
+    ctx->log_cap = capacity;
+    drop_graph(ctx);
+    return SWFE_OK;
+}
+
+int swfe_read_log(swfe_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!n_rows || (max_rows > 0 && !rows)) return fail(ctx, SWFE_E_INVALID_ARG, "null output");
+    *n_rows = 0;
+    if (ctx->log_every <= 0 || ctx->log_cap <= 0) return SWFE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<SysState> st;
+    int rc = read_states(ctx, st, s);
+    if (rc) return rc;
+    std::vector<double> ring((size_t)ctx->log_cap * SWFE_LOG_STRIDE);
+    HIPCHK(ctx, hipMemcpy(ring.data(), ctx->ptrs.log, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const int64_t events = st[0].step / ctx->log_every;
+    const int64_t keep = std::min<int64_t>(events, ctx->log_cap / ctx->n_sys);
+    int32_t n = 0;
+    for (int64_t e = events - keep + 1; e <= events; ++e)
+        for (int i = 0; i < ctx->n_sys && n < max_rows; ++i) {
+            const int64_t row = (e * ctx->n_sys + i) % ctx->log_cap;
+            memcpy(rows + (size_t)n * SWFE_LOG_STRIDE, ring.data() + row * SWFE_LOG_STRIDE,
+                   SWFE_LOG_STRIDE * sizeof(double));
+            ++n;
+        }
+    *n_rows = n;
+    return SWFE_OK;
+}
+
+int swfe_set_block(swfe_ctx *ctx, int32_t block, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (block == 0) {
+        int32_t chosen;
+        return swfe_autotune(ctx, &chosen, stream);
+    }
+    if (block != 64 && block != 128 && block != 256)
+        return fail(ctx, SWFE_E_INVALID_ARG, "block must be 64, 128 or 256");
+    ctx->block = block;
+    drop_graph(ctx);
+    build_tiles(ctx);
+    return upload_tables(ctx, (hipStream_t)stream);
+}
+
+int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    const int cand[3] = {64, 128, 256};
+    float best = 1e30f;
+    int best_b = 256;
+    for (int b : cand) {
+        int rc = swfe_set_block(ctx, b, stream);
+        if (rc) return rc;
+        rc = enqueue_forces(ctx, ctx->ptrs, 0, s);  // warm-up
+        if (rc) return rc;
+        HIPCHK(ctx, hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r) {
+            rc = enqueue_forces(ctx, ctx->ptrs, 0, s);
+            if (rc) return rc;
+        }
+        HIPCHK(ctx, hipEventRecord(e1, s));
+        HIPCHK(ctx, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_b = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (chosen_block) *chosen_block = best_b;
+    return swfe_set_block(ctx, best_b, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/swfe.h declares, and validates descriptors without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_10449_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def swfe():
+    from paper_2103_10449_amd import swfe as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2103_10449_amd import build
+        build.build()
+    m.load_library()
+    return m
+
+
+def test_exports_match_header(swfe):
+    hdr = open(os.path.join(ROOT, "include", "swfe.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(swfe_\w+)\(", hdr, re.M))
+    assert declared == set(swfe.EXPORTS)
+    lib = swfe.load_library()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _bytes(swfe, specs, params):
+    desc = swfe.system_descs(specs)
+    sw = swfe.sw_params_struct(params)
+    n = ctypes.c_size_t(0)
+    rc = swfe.load_library().swfe_workspace_bytes(desc, len(specs), ctypes.byref(sw), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_sizing(swfe, sw_params):
+    specs = inputs.config4(n_rep=8, steps=10).systems
+    rc, n = _bytes(swfe, specs, sw_params)
+    assert rc == 0
+    n_atoms = sum(s.n for s in specs)
+    assert n > n_atoms * (32 * 4 + 11 * 8)
+
+
+def test_box_too_small_rejected(swfe, sw_params):
+    x, box = inputs.diamond((1, 1, 1), 5.431)
+    s = inputs.SystemSpec(x=x, v=np.zeros_like(x), box=box, mode=inputs.MODE_FORCE)
+    rc, _ = _bytes(swfe, [s], sw_params)
+    assert rc == swfe.E_BOX_TOO_SMALL
+
+
+def test_invalid_descriptors_rejected(swfe, sw_params):
+    x, box = inputs.diamond((2, 2, 2), 5.431)
+    base = dict(x=x, v=np.zeros_like(x), box=box)
+    # dCCI partner must point back
+    a = inputs.SystemSpec(mode=inputs.MODE_DCCI_P, partner=1, T0=400, **base)
+    b = inputs.SystemSpec(mode=inputs.MODE_DCCI_P, partner=1, T0=400, **base)
+    assert _bytes(swfe, [a, b], sw_params)[0] == swfe.E_INVALID_ARG
+    # Frenkel-Ladd runs at fixed volume
+    c = inputs.SystemSpec(mode=inputs.MODE_FL, p_damp=1.0, T0=400, **base)
+    assert _bytes(swfe, [c], sw_params)[0] == swfe.E_INVALID_ARG
+    # barostat needs a temperature
+    d = inputs.SystemSpec(mode=inputs.MODE_NVT, p_damp=1.0, T0=0.0, **base)
+    assert _bytes(swfe, [d], sw_params)[0] == swfe.E_INVALID_ARG
+    # reversible scaling needs positive lambda
+    e = inputs.SystemSpec(mode=inputs.MODE_RS, sched_start=1.0, sched_end=0.0, T0=400, **base)
+    assert _bytes(swfe, [e], sw_params)[0] == swfe.E_INVALID_ARG
+
+
+def test_calls_before_init_fail_cleanly(swfe):
+    lib = swfe.load_library()
+    ctx = ctypes.c_void_p()
+    assert lib.swfe_create(ctypes.byref(ctx)) == 0
+    assert lib.swfe_step_switched(ctx, 10, 1, None) == swfe.E_STATE
+    assert b"not initialised" in lib.swfe_last_error(ctx)
+    lib.swfe_destroy(ctx)
