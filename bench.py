@@ -1,0 +1,208 @@
+"""Throughput of the batched switched-Hamiltonian step on one MI355X.
+
+Workload (default): 64 independent switching replicas of seeded uneven sizes
+(512-13824 atoms; diamond and beta-tin run Frenkel-Ladd lambda 1 -> 0 at
+1000 K, liquids run reversible scaling lambda 1 -> 0.5 at P = 0), all in one
+batch, one captured HIP-graph step replayed per MD step.  A "step" is one
+pass of the whole hot path over every replica: kick/drift/Langevin, cell
+binning, pair + three-body moments, force gather, reductions, lambda switch
+and work.  The timed K steps are K/2 forward + K/2 backward switching steps.
+
+Reported: atom-steps/s of the mixed path (FP32 terms, FP64 accumulation) as
+`value`, the plain FP64 path for the speedup, the |Delta F| gate between the
+two, the dominant kernel's roofline fraction (HIP events on the launch
+stream), and the CPU oracle's rate on a bounded sample of the same batch.
+"""
+import argparse
+import copy
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s per GPU, batched mixed vs plain FP64 at |ΔF|<1 meV/atom"
+
+# Algorithmic flops (each unique term counted once; exp, sqrt and division as
+# one flop each):
+C_PAIR = 56     # SW two-body energy, force and virial per unordered pair
+C_MOM = 29      # g(r) and the 11 three-body moments per (centre, neighbour)
+C_D3 = 95       # three-body force/virial contribution per (centre, neighbour)
+C_ATOM2 = 50    # per atom in pass 2: own three-body energy, Einstein, kick, kinetic energy
+PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
+
+
+def kernel_flops(name, n_atoms, ordered_pairs):
+    if name == "pass1":
+        return ordered_pairs / 2 * C_PAIR + ordered_pairs * C_MOM
+    if name == "pass2":
+        return ordered_pairs * C_D3 + n_atoms * C_ATOM2
+    return None
+
+
+def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps):
+    import torch
+    from paper_2103_10449_amd import swfe
+
+    half = steps // 2
+    wl = wl_builder(half)
+    specs = copy.deepcopy(wl.systems)
+    n_atoms = sum(s.n for s in specs)
+    eng = swfe.Engine(specs, P, dt=wl.dt, seed=seed, precision=precision)
+    block = eng.autotune()
+    print(f"# {precision}: engine ready, block {block}", file=sys.stderr, flush=True)
+    starts = [(s.sched_start, s.sched_end) for s in specs]
+    # warm-up at the start of the path (lambda held)
+    for s, (a, b) in zip(specs, starts):
+        s.sched_start, s.sched_end, s.sched_steps = a, a, 0
+    eng.set_schedule(specs)
+    eng.step(warmup, use_graph=True)
+    torch.cuda.synchronize()
+    eng.state()  # raises on a device error (non-finite, overflow, box)
+    print(f"# {precision}: {warmup} warm-up steps done", file=sys.stderr, flush=True)
+    W = {}
+    t_total = 0.0
+    ev_total = 0.0
+    for direction in ("fwd", "bwd"):
+        for s, (a, b) in zip(specs, starts):
+            s.sched_start, s.sched_end, s.sched_steps = (a, b, half) if direction == "fwd" else (b, a, half)
+        eng.set_schedule(specs)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        eng.step(half, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+        ev_total += e0.elapsed_time(e1) / 1e3
+        W[direction] = eng.work_integral()["W"]
+        print(f"# {precision}: {direction} {half} steps in {time.perf_counter() - t0:.3f} s",
+              file=sys.stderr, flush=True)
+    pairs, max_nb = eng.neighbor_stats()
+    prof = eng.profile_steps(profile_steps) if profile_steps else None
+    eng.close()
+    counts = np.array([s.n for s in specs], dtype=float)
+    dF = 0.5 * (W["fwd"] - W["bwd"]) / counts      # eV/atom per replica
+    return dict(n_atoms=n_atoms, wall=t_total, gpu=ev_total, steps=2 * half, dF=dF, block=block,
+                pairs=pairs, max_nb=max_nb, prof=prof, n_rep=len(specs))
+
+
+def cpu_baseline(wl_builder, P, seed, budget_s=12.0):
+    """The FP64 oracle on the same batch: full replica set, as many whole
+    steps as fit in about budget_s seconds (at least one)."""
+    from oracle import oracle as orc
+    wl = wl_builder(10)
+    systems = []
+    wl.systems = copy.deepcopy(wl.systems)
+    for s in wl.systems:
+        systems.append(orc.OSystem(x=s.x, v=s.v, box=s.box, mode=s.mode, x0=s.x0, partner=s.partner,
+                                   k_spring=s.k_spring, T0=s.T0, tau_damp=s.tau_damp, p_damp=s.p_damp,
+                                   pressure=s.pressure, stream=s.stream, sched_start=s.sched_start,
+                                   sched_end=s.sched_end, sched_steps=s.sched_steps))
+    o = orc.Oracle(systems, P, dt=wl.dt, seed=seed)
+    n = sum(s.n for s in systems)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        o.step()
+        k += 1
+        if time.perf_counter() - t0 > budget_s or k >= 10:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=n * k / dt, unit="atom-steps/s", cores=1, kind="oracle",
+                sample=f"all {len(systems)} replicas ({n} atoms) of the batched workload, {k} steps, "
+                       f"{dt:.1f} s, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--replicas", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the batched replicas of this workload do not "
+              f"communicate and are not split across GPUs (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2103_10449_amd import inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P = dict(inputs.SW_SILICON)
+    seed = inputs.SEED0
+    steps = max(2, args.steps - args.steps % 2)
+    base = inputs.config4(n_rep=args.replicas, steps=steps // 2)
+    print(f"# workload: {base.n_atoms} atoms in {len(base.systems)} replicas", file=sys.stderr, flush=True)
+    builder = lambda half: base
+
+    mixed = run_precision("mixed", builder, steps, args.warmup, P, seed, args.profile_steps)
+    print(f"# mixed: {mixed['n_atoms']} atoms, {mixed['steps']} steps in {mixed['wall']:.3f} s "
+          f"(block {mixed['block']}, {mixed['pairs'] / mixed['n_atoms']:.2f} neighbours/atom)", file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_precision("fp64", builder, steps, args.warmup, P, seed, args.profile_steps)
+        print(f"# fp64: {fp64['steps']} steps in {fp64['wall']:.3f} s", file=sys.stderr, flush=True)
+
+    value = mixed["n_atoms"] * mixed["steps"] / mixed["wall"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": mixed["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * mixed["wall"] / mixed["steps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.replicas} switching replicas, 512-13824 atoms each "
+                               "(diamond/beta-tin Frenkel-Ladd, liquid reversible scaling), one batch, "
+                               "HIP-graph step",
+                   "replicas": mixed["n_rep"], "atoms": mixed["n_atoms"], "precision": "mixed",
+                   "dt_ps": 0.001, "forward_steps": steps // 2, "backward_steps": steps // 2,
+                   "block": mixed["block"]},
+    }
+    if fp64 is not None:
+        v64 = fp64["n_atoms"] * fp64["steps"] / fp64["wall"]
+        diff = np.abs(mixed["dF"] - fp64["dF"])
+        out["fp64_value"] = v64
+        out["speedup_vs_fp64"] = value / v64
+        out["dF_gate"] = {"max_abs_diff_meV_per_atom": 1e3 * float(diff.max()),
+                          "mean_diff_meV_per_atom": 1e3 * float(np.mean(mixed["dF"] - fp64["dF"])),
+                          "pass": bool(abs(np.mean(mixed["dF"] - fp64["dF"])) < 1e-3)}
+    prof = mixed["prof"]
+    if prof:
+        name = max(prof, key=prof.get)
+        n_prof = args.profile_steps
+        avg = prof[name] / n_prof / 1e3              # s per launch
+        fl = kernel_flops(name, mixed["n_atoms"], mixed["pairs"])
+        ach = fl / avg / 1e12 if fl else None
+        out["roofline"] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": PEAK["mixed"] / 1e12,
+                           "unit": "TFLOP/s", "frac": (ach / (PEAK["mixed"] / 1e12)) if ach else None,
+                           "traffic": None, "avg_launch_us": 1e6 * avg,
+                           "per_kernel_us": {k: 1e3 * v / n_prof for k, v in prof.items()}}
+        if fp64 is not None and fp64["prof"]:
+            p64 = fp64["prof"]
+            avg64 = p64[name] / n_prof / 1e3
+            fl64 = kernel_flops(name, fp64["n_atoms"], fp64["pairs"])
+            out["roofline_fp64"] = {"kernel": name, "achieved": fl64 / avg64 / 1e12, "peak": PEAK["fp64"] / 1e12,
+                                    "frac": fl64 / avg64 / PEAK["fp64"],
+                                    "per_kernel_us": {k: 1e3 * v / n_prof for k, v in p64.items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(builder, P, seed)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -219,6 +219,18 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream);
 /* Sizes needed by the caller: total atoms and systems of the context. */
 int swfe_sizes(const swfe_ctx *ctx, int64_t *n_total, int32_t *n_sys);
 
+/* Measurement: run n_steps eager dynamics steps with HIP events recorded on
+ * the stream between the kernels of each step; ms[0..4] receive the summed
+ * durations of integrate, bin, pass1, pass2 and finalize (ms, host array of
+ * 5).  Synchronises.  The steps advance the systems like swfe_step_switched. */
+#define SWFE_NUM_KERNELS 5
+int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream);
+
+/* Neighbour statistics of the last force evaluation: total ordered pairs
+ * within the cutoff and the largest per-atom count (host outputs).
+ * Synchronises. */
+int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -712,4 +712,60 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
     return swfe_set_block(ctx, best_b, stream);
 }
 
+int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!ms || n_steps <= 0) return fail(ctx, SWFE_E_INVALID_ARG, "ms output and n_steps > 0 required");
+    hipStream_t s = (hipStream_t)stream;
+    const int nk = SWFE_NUM_KERNELS;
+    std::vector<hipEvent_t> ev((size_t)(nk + 1) * n_steps);
+    for (auto &e : ev) HIPCHK(ctx, hipEventCreate(&e));
+    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, s, ctx->ptrs.ctr, (int64_t)n_steps);
+    HIPCHK(ctx, hipGetLastError());
+    Ctl k = make_ctl(ctx, 1, 0);
+    HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, 2, ctx->log_every, ctx->log_cap, s));
+    for (int64_t i = 0; i < n_steps; ++i) {
+        hipEvent_t *e = &ev[(size_t)i * (nk + 1)];
+        HIPCHK(ctx, hipEventRecord(e[0], s));
+        HIPCHK(ctx, launch_integrate(k, ctx->ptrs, ctx->sw, ctx->block, s));
+        HIPCHK(ctx, hipEventRecord(e[1], s));
+        HIPCHK(ctx, launch_bin(k, ctx->ptrs, ctx->sw, s));
+        HIPCHK(ctx, hipEventRecord(e[2], s));
+        HIPCHK(ctx, launch_pass1(k, ctx->ptrs, ctx->sw, ctx->mixed, ctx->block, s));
+        HIPCHK(ctx, hipEventRecord(e[3], s));
+        HIPCHK(ctx, launch_pass2(k, ctx->ptrs, ctx->sw, ctx->mixed, ctx->block, s));
+        HIPCHK(ctx, hipEventRecord(e[4], s));
+        HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, 1, ctx->log_every, ctx->log_cap, s));
+        HIPCHK(ctx, hipEventRecord(e[5], s));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (int q = 0; q < nk; ++q) ms[q] = 0.0;
+    for (int64_t i = 0; i < n_steps; ++i)
+        for (int q = 0; q < nk; ++q) {
+            float t = 0.f;
+            HIPCHK(ctx, hipEventElapsedTime(&t, ev[(size_t)i * (nk + 1) + q], ev[(size_t)i * (nk + 1) + q + 1]));
+            ms[q] += t;
+        }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return SWFE_OK;
+}
+
+int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    std::vector<int32_t> nn((size_t)ctx->n_total);
+    HIPCHK(ctx, hipMemcpy(nn.data(), ctx->ptrs.nnb, nn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    int32_t mx = 0;
+    for (int32_t v : nn) {
+        tot += v;
+        mx = std::max(mx, v);
+    }
+    if (total_pairs) *total_pairs = tot;
+    if (max_per_atom) *max_per_atom = mx;
+    return SWFE_OK;
+}
+
 }  // extern "C"

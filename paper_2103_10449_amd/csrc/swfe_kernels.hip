@@ -315,15 +315,19 @@ __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
                         const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
                         const R ri = R(1) / r;
                         const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
-                        const R den = r - rc, di = R(1) / den;
+                        // Inside the cutoff in FP64 may round to r >= rc in the
+                        // term precision; the terms vanish there, so zero them.
+                        const R den = r - rc;
+                        const bool in = den < R(0);
+                        const R di = in ? R(1) / den : R(0);
                         const R sr = sig * ri;
                         const R sp = powi_or_pow(sr, sw.ip, pp);
                         const R sq = powi_or_pow(sr, sw.iq, qq);
-                        const R ex = exp(sig * di);
+                        const R ex = in ? exp(sig * di) : R(0);
                         const R br = B * sp - sq;
                         const R phi = eA * br * ex;
                         const R dphi = eA * ex * ((qq * sq - pp * B * sp) * ri - br * sig * di * di);
-                        const R g = exp(gam * sig * di);
+                        const R g = in ? exp(gam * sig * di) : R(0);
                         // moments
                         m_s += (double)g;
                         m_q += (double)(g * g);
@@ -449,8 +453,10 @@ __global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
             const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             const R ri = R(1) / r;
             const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
-            const R den = r - rc, di = R(1) / den;
-            const R g = exp(gam * sig * di);
+            const R den = r - rc;
+            const bool in = den < R(0);
+            const R di = in ? R(1) / den : R(0);
+            const R g = in ? exp(gam * sig * di) : R(0);
             const R dg = -g * gam * sig * di * di;
             R momJ[11];
 #pragma unroll

@@ -101,51 +101,49 @@ def liquid_number_density(rho_g_cm3: float = LIQUID_DENSITY_G_CM3,
 
 
 def liquid_rsa(n_atoms: int, g: np.random.Generator, density: Optional[float] = None,
-               d_min: float = 2.0, max_tries: int = 200000):
+               d_min: float = 2.0, max_tries: int = 200):
     """Random sequential addition of hard spheres of diameter d_min in a cubic box.
 
     A disordered (liquid-like) start at the given number density; with
     d_min = 2.0 A the packing fraction at 2.57 g/cm^3 is about 0.23, far below
-    the RSA jamming limit, so placement always succeeds.  Uses a coarse grid
-    of bins to keep the rejection test O(1).
+    the RSA jamming limit, so placement always succeeds.  Candidates are
+    tested against the atoms already placed in the 27 surrounding bins (bin
+    width >= d_min).  max_tries bounds the attempts per atom.
     """
     if density is None:
         density = liquid_number_density()
     L = (n_atoms / density) ** (1.0 / 3.0)
     nb = max(1, int(L // d_min))
     bw = L / nb
-    bins = {}
+    cap = 64
+    bins = -np.ones((nb, nb, nb, cap), dtype=np.int64)
+    fill = np.zeros((nb, nb, nb), dtype=np.int64)
+    rng_off = np.array([-1, 0, 1]) if nb >= 3 else np.arange(nb)
+    offs = np.array([(a, b, c) for a in rng_off for b in rng_off for c in rng_off])
     x = np.empty((n_atoms, 3))
+    d2 = d_min * d_min
     placed = 0
     tries = 0
-    d2 = d_min * d_min
     while placed < n_atoms:
         tries += 1
-        if tries > max_tries * max(1, n_atoms // 1000 + 1):
+        if tries > max_tries * n_atoms:
             raise RuntimeError("RSA failed to place all atoms")
         p = g.random(3) * L
-        b = tuple((p // bw).astype(int) % nb)
-        ok = True
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    key = ((b[0] + dx) % nb, (b[1] + dy) % nb, (b[2] + dz) % nb)
-                    for idx in bins.get(key, ()):
-                        d = x[idx] - p
-                        d -= L * np.round(d / L)
-                        if d @ d < d2:
-                            ok = False
-                            break
-                    if not ok:
-                        break
-                if not ok:
-                    break
-            if not ok:
-                break
-        if ok:
-            x[placed] = p
-            bins.setdefault(b, []).append(placed)
-            placed += 1
+        b = (p // bw).astype(np.int64) % nb
+        nbr = (b[None, :] + offs) % nb if nb >= 3 else offs
+        cand = bins[nbr[:, 0], nbr[:, 1], nbr[:, 2]].ravel()
+        cand = cand[cand >= 0]
+        if cand.size:
+            d = x[cand] - p
+            d -= L * np.round(d / L)
+            if np.einsum("ij,ij->i", d, d).min() < d2:
+                continue
+        if fill[b[0], b[1], b[2]] >= cap:
+            raise RuntimeError("RSA bin capacity exceeded")
+        x[placed] = p
+        bins[b[0], b[1], b[2], fill[b[0], b[1], b[2]]] = placed
+        fill[b[0], b[1], b[2]] += 1
+        placed += 1
     return x, np.array([L, L, L])
 
 

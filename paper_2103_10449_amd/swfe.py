@@ -64,7 +64,8 @@ class SystemState(ctypes.Structure):
 EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_bytes", "swfe_init_system",
            "swfe_build_neighbors", "swfe_compute_forces", "swfe_set_schedule", "swfe_step_switched",
            "swfe_work_integral", "swfe_get_state", "swfe_set_log", "swfe_read_log", "swfe_set_block",
-           "swfe_autotune", "swfe_sizes")
+           "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats")
+KERNEL_NAMES = ("integrate", "bin", "pass1", "pass2", "finalize")
 
 _lib = None
 
@@ -99,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "swfe_set_block": ([vp, i32, vp], ctypes.c_int),
         "swfe_autotune": ([vp, ctypes.POINTER(i32), vp], ctypes.c_int),
         "swfe_sizes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32)], ctypes.c_int),
+        "swfe_profile_steps": ([vp, i64, dp, vp], ctypes.c_int),
+        "swfe_neighbor_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32), vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -280,6 +283,17 @@ class Engine:
         b = ctypes.c_int32(0)
         self._check(self.lib.swfe_autotune(self.ctx, ctypes.byref(b), self._stream()))
         return int(b.value)
+
+    def profile_steps(self, n_steps: int) -> dict:
+        """Per-kernel HIP-event durations (ms, summed over n_steps eager steps)."""
+        ms = np.zeros(len(KERNEL_NAMES))
+        self._check(self.lib.swfe_profile_steps(self.ctx, int(n_steps), _dp(ms), self._stream()))
+        return dict(zip(KERNEL_NAMES, ms))
+
+    def neighbor_stats(self):
+        tot, mx = ctypes.c_int64(0), ctypes.c_int32(0)
+        self._check(self.lib.swfe_neighbor_stats(self.ctx, ctypes.byref(tot), ctypes.byref(mx), self._stream()))
+        return int(tot.value), int(mx.value)
 
     # --------------------------------------------------------------- views --
     def _unpack(self, t, s: int) -> np.ndarray:

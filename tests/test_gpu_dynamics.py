@@ -174,3 +174,23 @@ def test_einstein_switching_closed_form_batched(swfe, sw_params):
     assert abs(dF - exact) < max(4 * se, 0.01)
     assert abs(dF - exact) / 64 < 1e-3
     eng.close()
+
+
+def test_mixed_precision_dynamics_track_fp64(swfe, sw_params):
+    """FP32-term dynamics of a liquid (reversible scaling, NPT) and a
+    Frenkel-Ladd crystal stay finite and their work stays within 1 meV/atom
+    of the FP64 path with the same noise."""
+    mk = lambda: [liquid_spec(600, 90, mode=inputs.MODE_RS, T0=1700.0, tau_damp=0.1, p_damp=1.0,
+                              stream=0, sched_start=1.0, sched_end=0.5, sched_steps=400),
+                  diamond_spec(4, 91, mode=inputs.MODE_FL, k_spring=5.0, T0=1000.0, tau_damp=0.1,
+                               stream=1, sched_start=1.0, sched_end=0.0, sched_steps=400)]
+    res = {}
+    for prec in ("fp64", "mixed"):
+        eng = swfe.Engine(mk(), sw_params, seed=5, precision=prec)
+        eng.step(400)
+        res[prec] = eng.work_integral()["W"]
+        eng.close()
+    n = np.array([600, 512])
+    diff = np.abs(res["mixed"] - res["fp64"]) / n
+    print(f"mixed-fp64 work difference per atom: {diff}", flush=True)
+    assert np.all(diff < 1e-3)

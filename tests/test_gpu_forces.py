@@ -160,3 +160,19 @@ def test_determinism_bitwise(swfe, sw_params):
     assert np.array_equal(e1.forces(0), e2.forces(0))
     e1.close()
     e2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pair_just_inside_cutoff_is_finite(swfe, sw_params, prec):
+    """A pair inside the cutoff in FP64 whose FP32 distance rounds to the
+    cutoff: the terms vanish there and must stay finite."""
+    rc = sw_params["a"] * sw_params["sigma"]
+    x = np.array([[1.0, 1.0, 1.0], [1.0 + rc - 3e-9, 1.0, 1.0], [5.0, 6.0, 7.0]])
+    s = spec(x, [12.0, 12.0, 12.0])
+    eng = swfe.Engine([s], sw_params, precision=prec)
+    out = eng.compute_forces().cpu().numpy()[0]
+    ref = orc.sw_eval(s.x, s.box, sw_params)
+    assert np.all(np.isfinite(eng.forces(0))) and np.isfinite(out[0])
+    assert force_err(eng.forces(0), ref["F"]) < 1e-10
+    assert abs(out[0] - ref["E"]) < 1e-12
+    eng.close()
