@@ -34,6 +34,7 @@ C_MOM = 29      # g(r) and the 11 three-body moments per (centre, neighbour)
 C_D3 = 95       # three-body force/virial contribution per (centre, neighbour)
 C_ATOM2 = 50    # per atom in pass 2: own three-body energy, Einstein, kick, kinetic energy
 PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
+SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
 
 
 def kernel_flops(name, n_atoms, ordered_pairs):
@@ -56,10 +57,24 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps):
     block = eng.autotune()
     print(f"# {precision}: engine ready, block {block}", file=sys.stderr, flush=True)
     starts = [(s.sched_start, s.sched_end) for s in specs]
-    # warm-up at the start of the path (lambda held)
+    # warm-up at the start of the path (lambda held); its first steps pick
+    # the Verlet skin (rebuild frequency vs list length) by timing
     for s, (a, b) in zip(specs, starts):
         s.sched_start, s.sched_end, s.sched_steps = a, a, 0
     eng.set_schedule(specs)
+    best = None
+    for skin in SKINS:
+        eng.set_skin(skin)
+        eng.step(5, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.step(40, use_graph=True)
+        torch.cuda.synchronize()
+        dt_skin = time.perf_counter() - t0
+        if best is None or dt_skin < best[1]:
+            best = (skin, dt_skin)
+    eng.set_skin(best[0])
+    print(f"# {precision}: skin {best[0]} A", file=sys.stderr, flush=True)
     eng.step(warmup, use_graph=True)
     torch.cuda.synchronize()
     eng.state()  # raises on a device error (non-finite, overflow, box)
@@ -84,13 +99,15 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps):
         W[direction] = eng.work_integral()["W"]
         print(f"# {precision}: {direction} {half} steps in {time.perf_counter() - t0:.3f} s",
               file=sys.stderr, flush=True)
-    pairs, max_nb = eng.neighbor_stats()
+    pairs, max_nb, list_entries = eng.neighbor_stats()
+    n_rebuild = sum(x["n_rebuild"] for x in eng.state())
     prof = eng.profile_steps(profile_steps) if profile_steps else None
     eng.close()
     counts = np.array([s.n for s in specs], dtype=float)
     dF = 0.5 * (W["fwd"] - W["bwd"]) / counts      # eV/atom per replica
-    return dict(n_atoms=n_atoms, wall=t_total, gpu=ev_total, steps=2 * half, dF=dF, block=block,
-                pairs=pairs, max_nb=max_nb, prof=prof, n_rep=len(specs))
+    return dict(n_atoms=n_atoms, wall=t_total, gpu=ev_total, steps=2 * half, dF=dF, block=block, skin=best[0],
+                pairs=pairs, max_nb=max_nb, list_entries=list_entries, n_rebuild=n_rebuild, prof=prof,
+                n_rep=len(specs))
 
 
 def cpu_baseline(wl_builder, P, seed, budget_s=12.0):
@@ -171,7 +188,8 @@ def main():
                                "HIP-graph step",
                    "replicas": mixed["n_rep"], "atoms": mixed["n_atoms"], "precision": "mixed",
                    "dt_ps": 0.001, "forward_steps": steps // 2, "backward_steps": steps // 2,
-                   "block": mixed["block"]},
+                   "block": mixed["block"], "skin_A": mixed["skin"],
+                   "list_rebuilds_per_step": mixed["n_rebuild"] / (mixed["steps"] + args.warmup + 45 * len(SKINS))},
     }
     if fp64 is not None:
         v64 = fp64["n_atoms"] * fp64["steps"] / fp64["wall"]

@@ -44,7 +44,7 @@ typedef struct swfe_ctx swfe_ctx;
 #define SWFE_OK 0
 #define SWFE_E_INVALID_ARG -1   /* bad pointer, size, mode or parameter */
 #define SWFE_E_BOX_TOO_SMALL -2 /* a box length below twice the cutoff */
-#define SWFE_E_OVERFLOW -3      /* neighbour list (32 per atom) overflowed */
+#define SWFE_E_OVERFLOW -3      /* Verlet list (64 per atom) overflowed */
 #define SWFE_E_NONFINITE -4     /* NaN/Inf in an energy, force or position */
 #define SWFE_E_DCCI_SINGULAR -5 /* dCCI denominator or lambda out of range */
 #define SWFE_E_HIP -6           /* a HIP runtime call failed */
@@ -138,6 +138,7 @@ typedef struct {
     int64_t sched_k;   /* steps taken on the current schedule */
     int32_t err;       /* sticky device error bits of this system */
     int32_t pad;
+    int64_t n_rebuild; /* Verlet-list rebuilds of this system so far */
 } swfe_system_state;
 
 /* Per-system row written by swfe_compute_forces when out != NULL. */
@@ -219,17 +220,26 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream);
 /* Sizes needed by the caller: total atoms and systems of the context. */
 int swfe_sizes(const swfe_ctx *ctx, int64_t *n_total, int32_t *n_sys);
 
+/* Verlet-list skin (A, >= 0) of every system; the lists hold pairs within
+ * a sigma + skin and are rebuilt for a system when a pair now within the
+ * cutoff could be missing (displacements and box scaling since the build).
+ * Default 0.5 A.  Rebuilds the lists and re-evaluates the interaction at
+ * the current positions. */
+int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream);
+
 /* Measurement: run n_steps eager dynamics steps with HIP events recorded on
- * the stream between the kernels of each step; ms[0..4] receive the summed
- * durations of integrate, bin, pass1, pass2 and finalize (ms, host array of
- * 5).  Synchronises.  The steps advance the systems like swfe_step_switched. */
-#define SWFE_NUM_KERNELS 5
+ * the stream between the kernels of each step; ms[0..8] receive the summed
+ * durations of integrate, rebuild count, rebuild scan, rebuild scatter,
+ * rebuild order, rebuild list, pass1, pass2 and finalize (ms, host array of
+ * 9).  Synchronises.  The steps advance the systems like swfe_step_switched. */
+#define SWFE_NUM_KERNELS 9
 int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream);
 
-/* Neighbour statistics of the last force evaluation: total ordered pairs
- * within the cutoff and the largest per-atom count (host outputs).
- * Synchronises. */
-int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom, void *stream);
+/* Neighbour statistics of the last force evaluation (host outputs):
+ * ordered pairs within the cutoff, the largest per-atom count, and the
+ * Verlet-list entries (pairs within cutoff + skin).  Synchronises. */
+int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom,
+                        int64_t *list_entries, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1,9 +1,9 @@
 // swfe_api.hip -- host runtime behind the C-ABI declared in include/swfe.h.
 //
-// Holds the per-context tables (system descriptors, tile list, workspace
-// carve-up), validates inputs, enqueues the kernels of swfe_kernels.hip on
-// the caller's stream and, on request, captures one dynamics step into a HIP
-// graph that is replayed for every step.
+// Holds the per-context tables (system descriptors, reduction groups, the
+// tile list, the workspace carve-up), validates inputs, enqueues the kernels
+// of swfe_kernels.hip on the caller's stream and, on request, captures one
+// dynamics step into a HIP graph that is replayed for every step.
 #include "../../include/swfe.h"
 #include "swfe_internal.h"
 
@@ -24,19 +24,19 @@ constexpr double kMvv2e = 1.66053906660e-27 * 1e-20 / 1e-24 / 1.602176634e-19;  
 constexpr double kGpa = 1.602176634e-19 / 1e-30 / 1e9;                  // GPa per eV/A^3
 constexpr int kLogCapMax = 16384;                                       // rows of the log ring
 constexpr size_t kAlign = 256;
+constexpr double kDefaultSkin = 0.5;                                    // A
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-__global__ void k_set_ctr(int64_t *ctr, int64_t value) { ctr[0] = value; }
-
-__global__ void k_clear_err(SysState *st, int n_sys)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n_sys) st[s].err = 0;
-}
+struct Layout {
+    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s;
+    size_t perm, tperm, norder, rank, cellid, nnb, cell_count, cell_start, nl, nl_cnt, mom, e_s;
+    size_t part1, part2, disp_max, desc, state, tiles, groups, log, strain, total;
+};
 
 struct Plan {
     std::vector<SysDesc> desc;
+    std::vector<Group> groups;
     int64_t n_total = 0;
     int64_t cells = 0;       // sum of per-system cell capacities
     int64_t max_tiles = 0;   // tiles at the smallest block size
@@ -59,6 +59,7 @@ struct swfe_ctx {
     double dt = 0.001;
     uint64_t seed = 0;
     int block = 256;
+    double skin = kDefaultSkin;
     swfe_buffers buf{};
     DevPtrs ptrs{};
     int log_every = 0, log_cap = 0;
@@ -81,6 +82,12 @@ int fail(swfe_ctx *c, int code, const std::string &msg)
         hipError_t e_ = (expr);                                                           \
         if (e_ != hipSuccess)                                                             \
             return fail(ctx, SWFE_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define RCHK(expr)              \
+    do {                        \
+        int r_ = (expr);        \
+        if (r_) return r_;      \
     } while (0)
 
 bool is_dcci(int m) { return m == SWFE_MODE_DCCI_T || m == SWFE_MODE_DCCI_P; }
@@ -108,19 +115,19 @@ SwParams make_sw(const swfe_sw_params &p)
     return s;
 }
 
-// Validate descriptors and compute the per-system device descriptors and the
-// workspace layout.  Does not touch the GPU.
-int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw_params *p,
-                 double dt, Plan &out)
+// Validate descriptors; compute the device descriptors, the reduction groups
+// and the workspace layout.  Does not touch the GPU.
+int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw_params *p, double dt,
+                 double skin, Plan &out)
 {
     if (!d || !p || n_sys <= 0) return fail(ctx, SWFE_E_INVALID_ARG, "null descriptor/params or n_sys <= 0");
     if (!(p->a > 0 && p->sigma > 0 && p->mass > 0))
         return fail(ctx, SWFE_E_INVALID_ARG, "SW parameters need a > 0, sigma > 0, mass > 0");
     if (!(dt > 0)) return fail(ctx, SWFE_E_INVALID_ARG, "dt must be > 0");
+    if (!(skin >= 0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be >= 0");
     const double rc = p->a * p->sigma;
     Plan P;
-    int64_t off = 0;
-    int64_t tiles = 0, cells = 0;
+    int64_t off = 0, tiles = 0, cells = 0;
     for (int s = 0; s < n_sys; ++s) {
         const swfe_system_desc &q = d[s];
         char msg[256];
@@ -165,6 +172,8 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         sd.n = q.n_atoms;
         sd.mode = q.mode;
         sd.partner = is_dcci(q.mode) ? q.partner : -1;
+        // Cell capacity for boxes up to 1.3x the initial length; cells are at
+        // least rc + skin >= rc, so rc bounds the count for every skin.
         int64_t cap = 1;
         for (int k = 0; k < 3; ++k) {
             int n = (int)std::floor(q.box[k] * 1.3 / rc);
@@ -176,7 +185,6 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         sd.cell_base = (int32_t)cells;
         sd.cell_cap = (int32_t)cap;
         cells += cap;
-        sd.tile_begin = sd.tile_end = 0;
         sd.k_spring = q.k_spring;
         sd.T0 = q.T0;
         sd.tau_damp = q.tau_damp;
@@ -190,6 +198,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         sd.sigv = std::sqrt(kKB * q.T0 / (p->mass * kMvv2e));
         sd.acc = 1.0 / kMvv2e / p->mass;
         sd.mvv2e_m = 0.5 * p->mass * kMvv2e;
+        sd.skin = skin;
         sd.stream = q.stream;
         sd.s_start = q.sched_start;
         sd.s_end = q.sched_end;
@@ -198,7 +207,21 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         tiles += (q.n_atoms + 63) / 64;
         off += q.n_atoms;
     }
-    if (off >= ((int64_t)1 << 31) / 32) return fail(ctx, SWFE_E_INVALID_ARG, "too many atoms");
+    if (off >= ((int64_t)1 << 31) / kMaxList) return fail(ctx, SWFE_E_INVALID_ARG, "too many atoms");
+    for (int s = 0; s < n_sys; ++s) {
+        Group g{};
+        if (is_dcci(d[s].mode)) {
+            if (d[s].partner < s) continue;
+            g.s0 = s;
+            g.s1 = d[s].partner;
+        } else {
+            g.s0 = s;
+            g.s1 = -1;
+        }
+        P.desc[g.s0].group = (int32_t)P.groups.size();
+        if (g.s1 >= 0) P.desc[g.s1].group = (int32_t)P.groups.size();
+        P.groups.push_back(g);
+    }
     P.n_total = off;
     P.cells = cells;
     P.max_tiles = tiles;
@@ -209,55 +232,81 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         o = align_up(o + bytes);
         return at;
     };
-    const size_t n = (size_t)off;
-    L.cell_of = take(4 * n);
-    L.sorted = take(4 * n);
-    L.cell_count = take(4 * (size_t)cells);
-    L.cursor = take(4 * (size_t)cells);
-    L.cell_start = take(4 * ((size_t)cells + n_sys));
-    L.nbr = take(4 * n * kMaxNb);
+    const size_t n = (size_t)off, d4 = sizeof(double4);
+    L.xs = take(d4 * n);
+    L.vs = take(d4 * n);
+    L.fs = take(d4 * n);
+    L.x0s = take(d4 * n);
+    L.xb = take(d4 * n);
+    L.txs = take(d4 * n);
+    L.tvs = take(d4 * n);
+    L.tfs = take(d4 * n);
+    L.tx0s = take(d4 * n);
+    L.perm = take(4 * n);
+    L.tperm = take(4 * n);
+    L.norder = take(4 * n);
+    L.rank = take(4 * n);
+    L.cellid = take(4 * n);
     L.nnb = take(4 * n);
-    L.mom = take(8 * n * 11);
-    L.f2 = take(0);
+    L.cell_count = take(4 * (size_t)cells);
+    L.cell_start = take(4 * ((size_t)cells + n_sys));
+    L.nl = take(4 * n * kMaxList);
+    L.nl_cnt = take(4 * n);
+    L.mom = take(8 * 12 * n);
+    L.e_s = take(8 * n);
     L.part1 = take(8 * (size_t)tiles * kNumPart);
     L.part2 = take(8 * (size_t)tiles * kNumPart);
+    L.disp_max = take(8 * 2 * (size_t)n_sys);
     L.desc = take(sizeof(SysDesc) * n_sys);
     L.state = take(sizeof(SysState) * n_sys);
     L.tiles = take(sizeof(Tile) * (size_t)tiles);
+    L.groups = take(sizeof(Group) * P.groups.size());
     L.log = take(8 * (size_t)kLogCapMax * SWFE_LOG_STRIDE);
-    L.misc = take(8 * 4 + 8 * 9 * (size_t)n_sys);
+    L.strain = take(8 * 3 * (size_t)n_sys);
     L.total = o;
     out = std::move(P);
     return SWFE_OK;
 }
 
+// Tiles of `block` atoms, laid out group by group so that the tiles of a
+// group (a system, or both phases of a dCCI pair) are contiguous.
 void build_tiles(swfe_ctx *c)
 {
     c->tiles.clear();
-    for (int s = 0; s < c->n_sys; ++s) {
-        SysDesc &d = c->plan.desc[s];
-        d.tile_begin = (int32_t)c->tiles.size();
-        for (int64_t a = 0; a < d.n; a += c->block) {
-            Tile t{};
-            t.sys = s;
-            t.start = (int32_t)(d.off + a);
-            t.count = (int32_t)std::min<int64_t>(c->block, d.n - a);
-            c->tiles.push_back(t);
+    for (Group &g : c->plan.groups) {
+        g.tile_begin = (int32_t)c->tiles.size();
+        for (int q = 0; q < (g.s1 >= 0 ? 2 : 1); ++q) {
+            const int s = q == 0 ? g.s0 : g.s1;
+            SysDesc &d = c->plan.desc[s];
+            d.tile_begin = (int32_t)c->tiles.size();
+            for (int64_t a = 0; a < d.n; a += c->block) {
+                Tile t{};
+                t.sys = s;
+                t.start = (int32_t)(d.off + a);
+                t.count = (int32_t)std::min<int64_t>(c->block, d.n - a);
+                c->tiles.push_back(t);
+            }
+            d.tile_end = (int32_t)c->tiles.size();
         }
-        d.tile_end = (int32_t)c->tiles.size();
+        g.tile_end = (int32_t)c->tiles.size();
     }
 }
 
-Ctl make_ctl(const swfe_ctx *c, int in_step, int flags)
+Ctl make_ctl(const swfe_ctx *c, int in_step, int flags, int force_rebuild)
 {
     Ctl k{};
     k.n_total = c->n_total;
     k.n_sys = c->n_sys;
     k.n_tiles = (int32_t)c->tiles.size();
+    k.n_groups = (int32_t)c->plan.groups.size();
+    k.xcd_stride = (k.n_tiles + 7) / 8;
     k.dt = c->dt;
     k.seed = c->seed;
     k.flags = flags;
     k.in_step = in_step;
+    k.force_rebuild = force_rebuild;
+    k.log_every = c->log_every;
+    k.log_cap = c->log_cap;
     return k;
 }
 
@@ -276,29 +325,41 @@ int upload_tables(swfe_ctx *c, hipStream_t s)
                              hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync((void *)c->ptrs.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(),
                              hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync((void *)c->ptrs.groups, c->plan.groups.data(),
+                             sizeof(Group) * c->plan.groups.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return SWFE_OK;
 }
 
-int enqueue_forces(swfe_ctx *c, const DevPtrs &p, int flags, hipStream_t s)
+int enqueue_rebuild(swfe_ctx *c, const DevPtrs &p, const Ctl &k, hipStream_t s)
 {
-    Ctl k = make_ctl(c, 0, flags);
-    HIPCHK(c, launch_assign_cells(k, p, c->sw, c->block, s));
-    HIPCHK(c, launch_bin(k, p, c->sw, s));
+    for (int stage = 0; stage < kRebuildStages; ++stage)
+        HIPCHK(c, launch_rebuild(k, p, c->sw, c->block, stage, s));
+    return SWFE_OK;
+}
+
+// Caller positions -> forced list rebuild -> interaction -> caller arrays
+// (scatter_what: bits of k_scatter).
+int enqueue_forces(swfe_ctx *c, const DevPtrs &p, int flags, int scatter_what, hipStream_t s)
+{
+    Ctl k = make_ctl(c, 0, flags, 1);
+    HIPCHK(c, launch_gather(k, p, c->block, 0, s));
+    RCHK(enqueue_rebuild(c, p, k, s));
     HIPCHK(c, launch_pass1(k, p, c->sw, c->mixed, c->block, s));
     HIPCHK(c, launch_pass2(k, p, c->sw, c->mixed, c->block, s));
-    HIPCHK(c, launch_finalize(k, p, c->sw, 0, c->log_every, c->log_cap, s));
+    HIPCHK(c, launch_finalize(k, p, c->sw, s));
+    HIPCHK(c, launch_scatter(k, p, c->block, scatter_what, s));
     return SWFE_OK;
 }
 
 int enqueue_step(swfe_ctx *c, hipStream_t s)
 {
-    Ctl k = make_ctl(c, 1, 0);
+    Ctl k = make_ctl(c, 1, 0, 0);
     HIPCHK(c, launch_integrate(k, c->ptrs, c->sw, c->block, s));
-    HIPCHK(c, launch_bin(k, c->ptrs, c->sw, s));
+    RCHK(enqueue_rebuild(c, c->ptrs, k, s));
     HIPCHK(c, launch_pass1(k, c->ptrs, c->sw, c->mixed, c->block, s));
     HIPCHK(c, launch_pass2(k, c->ptrs, c->sw, c->mixed, c->block, s));
-    HIPCHK(c, launch_finalize(k, c->ptrs, c->sw, 1, c->log_every, c->log_cap, s));
+    HIPCHK(c, launch_finalize(k, c->ptrs, c->sw, s));
     return SWFE_OK;
 }
 
@@ -320,12 +381,12 @@ int take_device_error(swfe_ctx *c, const std::vector<SysState> &st, hipStream_t 
             who = i;
         }
     if (!bits) return SWFE_OK;
-    hipLaunchKernelGGL(k_clear_err, dim3((c->n_sys + 63) / 64), dim3(64), 0, s, c->ptrs.state, c->n_sys);
-    HIPCHK(c, hipGetLastError());
+    Ctl k = make_ctl(c, 0, 0, 0);
+    HIPCHK(c, launch_clear_err(k, c->ptrs, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    char msg[160];
+    char msg[200];
     const char *what = (bits & ERR_NONFINITE) ? "non-finite value"
-                       : (bits & ERR_OVERFLOW) ? "neighbour list overflow (more than 32 within the cutoff)"
+                       : (bits & ERR_OVERFLOW) ? "Verlet list overflow (more than 64 within cutoff + skin)"
                        : (bits & ERR_BOX) ? "box length fell below twice the cutoff"
                                           : "dCCI update singular (|dv| or denominator too small, or lambda out of (0.05, 20))";
     snprintf(msg, sizeof msg, "system %d: %s", who, what);
@@ -361,8 +422,7 @@ int swfe_workspace_bytes(const swfe_system_desc *d, int32_t n_sys, const swfe_sw
 {
     if (!bytes) return SWFE_E_INVALID_ARG;
     Plan P;
-    int rc = plan_systems(nullptr, d, n_sys, p, 0.001, P);
-    if (rc) return rc;
+    RCHK(plan_systems(nullptr, d, n_sys, p, 0.001, kDefaultSkin, P));
     *bytes = P.lay.total;
     return SWFE_OK;
 }
@@ -386,8 +446,7 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     if (precision != SWFE_PREC_FP64 && precision != SWFE_PREC_MIXED)
         return fail(ctx, SWFE_E_INVALID_ARG, "precision must be SWFE_PREC_FP64 or SWFE_PREC_MIXED");
     Plan P;
-    int rc = plan_systems(ctx, d, n_sys, p, dt, P);
-    if (rc) return rc;
+    RCHK(plan_systems(ctx, d, n_sys, p, dt, ctx->skin, P));
     for (int s = 0; s < n_sys; ++s)
         if (d[s].mode == SWFE_MODE_FL && !b->x0)
             return fail(ctx, SWFE_E_INVALID_ARG, "Frenkel-Ladd systems need Einstein anchors x0");
@@ -419,23 +478,35 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     q.f = b->f;
     q.x0 = b->x0;
     q.e_atom = b->e_atom;
-    q.cell_of = (int32_t *)(w + L.cell_of);
-    q.sorted = (int32_t *)(w + L.sorted);
-    q.cell_count = (int32_t *)(w + L.cell_count);
-    q.cursor = (int32_t *)(w + L.cursor);
-    q.cell_start = (int32_t *)(w + L.cell_start);
-    q.nbr = (int32_t *)(w + L.nbr);
+    q.xs = (double4 *)(w + L.xs);
+    q.vs = (double4 *)(w + L.vs);
+    q.fs = (double4 *)(w + L.fs);
+    q.x0s = (double4 *)(w + L.x0s);
+    q.xb = (double4 *)(w + L.xb);
+    q.txs = (double4 *)(w + L.txs);
+    q.tvs = (double4 *)(w + L.tvs);
+    q.tfs = (double4 *)(w + L.tfs);
+    q.tx0s = (double4 *)(w + L.tx0s);
+    q.perm = (int32_t *)(w + L.perm);
+    q.tperm = (int32_t *)(w + L.tperm);
+    q.norder = (int32_t *)(w + L.norder);
+    q.rank = (int32_t *)(w + L.rank);
+    q.cellid = (int32_t *)(w + L.cellid);
     q.nnb = (int32_t *)(w + L.nnb);
-    q.mom = (double *)(w + L.mom);
-    q.f2 = nullptr;
+    q.cell_count = (int32_t *)(w + L.cell_count);
+    q.cell_start = (int32_t *)(w + L.cell_start);
+    q.nl = (int32_t *)(w + L.nl);
+    q.nl_cnt = (int32_t *)(w + L.nl_cnt);
+    q.mom = (void *)(w + L.mom);
+    q.e_s = (double *)(w + L.e_s);
     q.part1 = (double *)(w + L.part1);
     q.part2 = (double *)(w + L.part2);
+    q.disp_max = (double *)(w + L.disp_max);
     q.desc = (const SysDesc *)(w + L.desc);
     q.state = (SysState *)(w + L.state);
     q.tiles = (const Tile *)(w + L.tiles);
+    q.groups = (const Group *)(w + L.groups);
     q.log = (double *)(w + L.log);
-    q.ctr = (int64_t *)(w + L.misc);
-    q.misc = nullptr;
 
     std::vector<SysState> st(n_sys);
     for (int i = 0; i < n_sys; ++i) {
@@ -443,23 +514,22 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
         memset(&x, 0, sizeof x);
         for (int k = 0; k < 3; ++k) {
             x.box[k] = d[i].box[k];
+            x.box_build[k] = d[i].box[k];
             x.pscale[k] = 1.0;
         }
         x.decay = x.phi = x.grow = x.psi = 1.0;
     }
     HIPCHK(ctx, hipMemcpyAsync(q.state, st.data(), sizeof(SysState) * n_sys, hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, hipMemsetAsync(w + L.misc, 0, 32, s));
-    rc = upload_tables(ctx, s);
-    if (rc) return rc;
-    Ctl k = make_ctl(ctx, 0, 0);
+    HIPCHK(ctx, hipMemsetAsync(q.cell_count, 0, 4 * (size_t)ctx->plan.cells, s));
+    HIPCHK(ctx, hipMemsetAsync(q.disp_max, 0, 8 * 2 * (size_t)n_sys, s));
+    RCHK(upload_tables(ctx, s));
+    Ctl k = make_ctl(ctx, 0, 0, 1);
+    HIPCHK(ctx, launch_iota(k, q, ctx->block, s));
     HIPCHK(ctx, launch_reset_schedule(k, q, s));
-    rc = enqueue_forces(ctx, q, 0, s);
-    if (rc) return rc;
+    RCHK(enqueue_forces(ctx, q, 0, 2 | 4, s));
     std::vector<SysState> now;
-    rc = read_states(ctx, now, s);
-    if (rc) return rc;
-    rc = take_device_error(ctx, now, s);
-    if (rc) return rc;
+    RCHK(read_states(ctx, now, s));
+    RCHK(take_device_error(ctx, now, s));
     ctx->ready = true;
     return SWFE_OK;
 }
@@ -468,9 +538,10 @@ int swfe_build_neighbors(swfe_ctx *ctx, void *stream)
 {
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     hipStream_t s = (hipStream_t)stream;
-    Ctl k = make_ctl(ctx, 0, 0);
-    HIPCHK(ctx, launch_assign_cells(k, ctx->ptrs, ctx->sw, ctx->block, s));
-    HIPCHK(ctx, launch_bin(k, ctx->ptrs, ctx->sw, s));
+    Ctl k = make_ctl(ctx, 0, 0, 1);
+    HIPCHK(ctx, launch_gather(k, ctx->ptrs, ctx->block, 1, s));
+    RCHK(enqueue_rebuild(ctx, ctx->ptrs, k, s));
+    HIPCHK(ctx, launch_scatter(k, ctx->ptrs, ctx->block, 1 | 2, s));
     return SWFE_OK;
 }
 
@@ -484,8 +555,8 @@ int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain, con
     p.grad_scale = grad_scale;
     p.grad_x = grad_x;
     p.out = out;
-    Ctl k = make_ctl(ctx, 0, (int)flags);
-    double *diag = (double *)((char *)ctx->buf.workspace + ctx->plan.lay.misc + 32);
+    Ctl k = make_ctl(ctx, 0, (int)flags, 1);
+    double *diag = (double *)((char *)ctx->buf.workspace + ctx->plan.lay.strain);
     if (flags & SWFE_STRAIN) {
         if (!strain) return fail(ctx, SWFE_E_INVALID_ARG, "SWFE_STRAIN needs a strain array");
         std::vector<double> dg(3 * ctx->n_sys);
@@ -503,8 +574,7 @@ int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain, con
         HIPCHK(ctx, hipMemcpy(diag, dg.data(), sizeof(double) * dg.size(), hipMemcpyHostToDevice));
         HIPCHK(ctx, launch_set_pscale(k, p, diag, s));
     }
-    int rc = enqueue_forces(ctx, p, (int)flags, s);
-    if (rc) return rc;
+    RCHK(enqueue_forces(ctx, p, (int)flags, 2 | 4 | 8, s));
     if (flags & SWFE_STRAIN) HIPCHK(ctx, launch_set_pscale(k, p, nullptr, s));
     return SWFE_OK;
 }
@@ -515,24 +585,20 @@ int swfe_set_schedule(swfe_ctx *ctx, const swfe_system_desc *d, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (d) {
         for (int i = 0; i < ctx->n_sys; ++i) {
-            swfe_system_desc q = ctx->hdesc[i];
-            q.sched_start = d[i].sched_start;
-            q.sched_end = d[i].sched_end;
-            q.sched_steps = d[i].sched_steps;
-            ctx->hdesc[i] = q;
+            ctx->hdesc[i].sched_start = d[i].sched_start;
+            ctx->hdesc[i].sched_end = d[i].sched_end;
+            ctx->hdesc[i].sched_steps = d[i].sched_steps;
         }
         Plan P;
-        int rc = plan_systems(ctx, ctx->hdesc.data(), ctx->n_sys, &ctx->hsw, ctx->dt, P);
-        if (rc) return rc;
+        RCHK(plan_systems(ctx, ctx->hdesc.data(), ctx->n_sys, &ctx->hsw, ctx->dt, ctx->skin, P));
         for (int i = 0; i < ctx->n_sys; ++i) {
             ctx->plan.desc[i].s_start = d[i].sched_start;
             ctx->plan.desc[i].s_end = d[i].sched_end;
             ctx->plan.desc[i].s_steps = d[i].sched_steps;
         }
-        int r2 = upload_tables(ctx, s);
-        if (r2) return r2;
+        RCHK(upload_tables(ctx, s));
     }
-    Ctl k = make_ctl(ctx, 0, 0);
+    Ctl k = make_ctl(ctx, 0, 0, 0);
     HIPCHK(ctx, launch_reset_schedule(k, ctx->ptrs, s));
     return SWFE_OK;
 }
@@ -543,38 +609,35 @@ int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *
     if (n_steps < 0) return fail(ctx, SWFE_E_INVALID_ARG, "n_steps < 0");
     if (n_steps == 0) return SWFE_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, s, ctx->ptrs.ctr, (int64_t)n_steps);
-    HIPCHK(ctx, hipGetLastError());
-    Ctl k = make_ctl(ctx, 1, 0);
-    HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, 2, ctx->log_every, ctx->log_cap, s));
+    Ctl k = make_ctl(ctx, 1, 0, 0);
+    HIPCHK(ctx, launch_gather(k, ctx->ptrs, ctx->block, 1, s));
+    HIPCHK(ctx, launch_begin_step(k, ctx->ptrs, ctx->sw, n_steps, s));
     if (!use_graph) {
-        for (int64_t i = 0; i < n_steps; ++i) {
-            int rc = enqueue_step(ctx, s);
-            if (rc) return rc;
+        for (int64_t i = 0; i < n_steps; ++i) RCHK(enqueue_step(ctx, s));
+    } else {
+        if (!ctx->graph_valid) {
+            // Capture one step on a library-owned stream (the caller's stream
+            // may be the legacy default stream, which cannot be captured); the
+            // graph is then launched on the caller's stream.
+            drop_graph(ctx);
+            if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_step(ctx, ctx->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            HIPCHK(ctx, e);
+            ctx->graph = g;
+            HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+            ctx->graph_valid = true;
         }
-        return SWFE_OK;
+        for (int64_t i = 0; i < n_steps; ++i) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));
     }
-    if (!ctx->graph_valid) {
-        // Capture one step on a library-owned stream (the caller's stream may
-        // be the legacy default stream, which cannot be captured); the graph
-        // is then launched on the caller's stream.
-        drop_graph(ctx);
-        if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(ctx, ctx->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
-        HIPCHK(ctx, e);
-        ctx->graph = g;
-        HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
-        ctx->graph_valid = true;
-    }
-    for (int64_t i = 0; i < n_steps; ++i) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, s));
+    HIPCHK(ctx, launch_scatter(k, ctx->ptrs, ctx->block, 1 | 2, s));
     return SWFE_OK;
 }
 
@@ -584,8 +647,7 @@ int swfe_get_state(swfe_ctx *ctx, swfe_system_state *out, void *stream)
     if (!out) return fail(ctx, SWFE_E_INVALID_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
     std::vector<SysState> st;
-    int rc = read_states(ctx, st, s);
-    if (rc) return rc;
+    RCHK(read_states(ctx, st, s));
     for (int i = 0; i < ctx->n_sys; ++i) {
         swfe_system_state &o = out[i];
         const SysState &x = st[i];
@@ -605,6 +667,7 @@ int swfe_get_state(swfe_ctx *ctx, swfe_system_state *out, void *stream)
         o.sched_k = x.k;
         o.err = x.err;
         o.pad = 0;
+        o.n_rebuild = x.n_rebuild;
     }
     return take_device_error(ctx, st, s);
 }
@@ -614,8 +677,7 @@ int swfe_work_integral(swfe_ctx *ctx, double *W, double *lam, double *Ps, int64_
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     hipStream_t s = (hipStream_t)stream;
     std::vector<SysState> st;
-    int rc = read_states(ctx, st, s);
-    if (rc) return rc;
+    RCHK(read_states(ctx, st, s));
     for (int i = 0; i < ctx->n_sys; ++i) {
         if (W) W[i] = st[i].W;
         if (lam) lam[i] = st[i].lam;
@@ -644,8 +706,7 @@ int swfe_read_log(swfe_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows
     if (ctx->log_every <= 0 || ctx->log_cap <= 0) return SWFE_OK;
     hipStream_t s = (hipStream_t)stream;
     std::vector<SysState> st;
-    int rc = read_states(ctx, st, s);
-    if (rc) return rc;
+    RCHK(read_states(ctx, st, s));
     std::vector<double> ring((size_t)ctx->log_cap * SWFE_LOG_STRIDE);
     HIPCHK(ctx, hipMemcpy(ring.data(), ctx->ptrs.log, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
     const int64_t events = st[0].step / ctx->log_every;
@@ -671,10 +732,23 @@ int swfe_set_block(swfe_ctx *ctx, int32_t block, void *stream)
     }
     if (block != 64 && block != 128 && block != 256)
         return fail(ctx, SWFE_E_INVALID_ARG, "block must be 64, 128 or 256");
+    hipStream_t s = (hipStream_t)stream;
     ctx->block = block;
     drop_graph(ctx);
     build_tiles(ctx);
-    return upload_tables(ctx, (hipStream_t)stream);
+    RCHK(upload_tables(ctx, s));
+    return enqueue_forces(ctx, ctx->ptrs, 0, 2, s);
+}
+
+int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!(skin >= 0.0 && skin < 5.0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be in [0, 5) A");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->skin = skin;
+    for (auto &d : ctx->plan.desc) d.skin = skin;
+    RCHK(upload_tables(ctx, s));
+    return enqueue_forces(ctx, ctx->ptrs, 0, 2, s);
 }
 
 int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
@@ -688,14 +762,13 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
     float best = 1e30f;
     int best_b = 256;
     for (int b : cand) {
-        int rc = swfe_set_block(ctx, b, stream);
-        if (rc) return rc;
-        rc = enqueue_forces(ctx, ctx->ptrs, 0, s);  // warm-up
-        if (rc) return rc;
+        RCHK(swfe_set_block(ctx, b, stream));
+        Ctl k = make_ctl(ctx, 0, 0, 0);
+        // time the force passes on the list just built
         HIPCHK(ctx, hipEventRecord(e0, s));
         for (int r = 0; r < 5; ++r) {
-            rc = enqueue_forces(ctx, ctx->ptrs, 0, s);
-            if (rc) return rc;
+            HIPCHK(ctx, launch_pass1(k, ctx->ptrs, ctx->sw, ctx->mixed, ctx->block, s));
+            HIPCHK(ctx, launch_pass2(k, ctx->ptrs, ctx->sw, ctx->mixed, ctx->block, s));
         }
         HIPCHK(ctx, hipEventRecord(e1, s));
         HIPCHK(ctx, hipEventSynchronize(e1));
@@ -720,24 +793,26 @@ int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)
     const int nk = SWFE_NUM_KERNELS;
     std::vector<hipEvent_t> ev((size_t)(nk + 1) * n_steps);
     for (auto &e : ev) HIPCHK(ctx, hipEventCreate(&e));
-    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, s, ctx->ptrs.ctr, (int64_t)n_steps);
-    HIPCHK(ctx, hipGetLastError());
-    Ctl k = make_ctl(ctx, 1, 0);
-    HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, 2, ctx->log_every, ctx->log_cap, s));
+    Ctl k = make_ctl(ctx, 1, 0, 0);
+    HIPCHK(ctx, launch_gather(k, ctx->ptrs, ctx->block, 1, s));
+    HIPCHK(ctx, launch_begin_step(k, ctx->ptrs, ctx->sw, n_steps, s));
     for (int64_t i = 0; i < n_steps; ++i) {
         hipEvent_t *e = &ev[(size_t)i * (nk + 1)];
         HIPCHK(ctx, hipEventRecord(e[0], s));
         HIPCHK(ctx, launch_integrate(k, ctx->ptrs, ctx->sw, ctx->block, s));
         HIPCHK(ctx, hipEventRecord(e[1], s));
-        HIPCHK(ctx, launch_bin(k, ctx->ptrs, ctx->sw, s));
-        HIPCHK(ctx, hipEventRecord(e[2], s));
+        for (int stage = 0; stage < kRebuildStages; ++stage) {
+            HIPCHK(ctx, launch_rebuild(k, ctx->ptrs, ctx->sw, ctx->block, stage, s));
+            HIPCHK(ctx, hipEventRecord(e[2 + stage], s));
+        }
         HIPCHK(ctx, launch_pass1(k, ctx->ptrs, ctx->sw, ctx->mixed, ctx->block, s));
-        HIPCHK(ctx, hipEventRecord(e[3], s));
+        HIPCHK(ctx, hipEventRecord(e[2 + kRebuildStages], s));
         HIPCHK(ctx, launch_pass2(k, ctx->ptrs, ctx->sw, ctx->mixed, ctx->block, s));
-        HIPCHK(ctx, hipEventRecord(e[4], s));
-        HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, 1, ctx->log_every, ctx->log_cap, s));
-        HIPCHK(ctx, hipEventRecord(e[5], s));
+        HIPCHK(ctx, hipEventRecord(e[3 + kRebuildStages], s));
+        HIPCHK(ctx, launch_finalize(k, ctx->ptrs, ctx->sw, s));
+        HIPCHK(ctx, hipEventRecord(e[4 + kRebuildStages], s));
     }
+    HIPCHK(ctx, launch_scatter(k, ctx->ptrs, ctx->block, 1 | 2, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     for (int q = 0; q < nk; ++q) ms[q] = 0.0;
     for (int64_t i = 0; i < n_steps; ++i)
@@ -750,21 +825,25 @@ int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)
     return SWFE_OK;
 }
 
-int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom, void *stream)
+int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom, int64_t *list_entries,
+                        void *stream)
 {
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(ctx, hipStreamSynchronize(s));
-    std::vector<int32_t> nn((size_t)ctx->n_total);
+    std::vector<int32_t> nn((size_t)ctx->n_total), nl((size_t)ctx->n_total);
     HIPCHK(ctx, hipMemcpy(nn.data(), ctx->ptrs.nnb, nn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    int64_t tot = 0;
+    HIPCHK(ctx, hipMemcpy(nl.data(), ctx->ptrs.nl_cnt, nl.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int64_t tot = 0, ltot = 0;
     int32_t mx = 0;
-    for (int32_t v : nn) {
-        tot += v;
-        mx = std::max(mx, v);
+    for (size_t i = 0; i < nn.size(); ++i) {
+        tot += nn[i];
+        ltot += nl[i];
+        mx = std::max(mx, nn[i]);
     }
     if (total_pairs) *total_pairs = tot;
     if (max_per_atom) *max_per_atom = mx;
+    if (list_entries) *list_entries = ltot;
     return SWFE_OK;
 }
 

@@ -1,28 +1,37 @@
 // swfe_kernels.hip -- HIP kernels for gfx950 of the switched-Hamiltonian
 // Stillinger-Weber silicon step.
 //
-// One MD step is five launches over all systems at once:
-//   integrate  per atom:  B kick, A drift, O Langevin, A drift, cell index
-//   bin        per system (one 1024-thread workgroup): deterministic counting
-//              sort of atoms by cell (ties in atom order)
-//   pass1      per tile of cell-sorted atoms: 27-cell search, neighbour
-//              list, pair terms, and the 11 three-body moments per atom
-//   pass2      per tile: three-body force gather from own and neighbour
-//              moments (no atomics), Einstein springs, final B kick,
-//              per-tile partial sums
-//   finalize   one workgroup: per-system reductions in a fixed order, the
-//              barostat, the lambda switch and its work increment, dCCI
-//              coupling, integrator factors for the next step.
+// Data layout.  Internally every atom array lives in cell-sorted order as
+// double4 (x, y, z, -), one contiguous range per system; perm[t] is the
+// caller's atom index at sorted position t.  Neighbour lists hold sorted
+// positions, so neighbours of a tile are nearby in memory.
+//
+// One dynamics step is nine launches over all systems at once:
+//   integrate    B kick, A drift, O Langevin, A drift; per-tile maximum
+//                displacement since the last list build
+//   rebuild 0-4  (only systems whose list may miss a pair do any work)
+//                0 count:   cell index and rank within the cell
+//                1 scan:    per-system cell starts
+//                2 scatter: atom data into its cell's segment (staging)
+//                3 order:   in-cell order by the caller's atom index
+//                4 list:    Verlet list within rc + skin from the 27 cells
+//   pass1        pair terms and the 11 three-body moments per atom
+//   pass2        three-body force gather from own and neighbour moments,
+//                Einstein springs, final B kick, per-tile partial sums
+//   finalize     one block per group (a system or a dCCI pair): fixed-order
+//                reduction of its tiles, the barostat, the lambda switch and
+//                work increment, the dCCI coupling and the integrator
+//                factors of the next step.
 //
 // Three-body term in moment form.  With g_j = g(r_ij), u_j = r_ij/|r_ij| and
 // the moments of centre i
 //     s = sum g_j, q = sum g_j^2, v = sum g_j u_j, M = sum g_j u_j u_j^T,
 // the triplet sum sum_{j<k} (u_j.u_k - c0)^2 g_j g_k equals
 //     Phi/2,  Phi = |M|_F^2 - 2 c0 |v|^2 + c0^2 s^2 - (1 - c0)^2 q,
-// so E3_i = (lambda_sw eps / 2) Phi_i.  dE3_i/dr_ij depends only on r_ij and
-// centre i's moments, which turns the three-body force into an O(n) gather.
-// No floating-point atomics are used anywhere: every sum has a fixed order,
-// so runs are bitwise reproducible.
+// so E3_i = (lambda_sw eps / 2) Phi_i, and dE3_i/dr_ij depends only on r_ij
+// and centre i's moments: the three-body force becomes an O(n) gather.
+// No floating-point atomics are used: every sum has a fixed order, so runs
+// are bitwise reproducible.
 #include "swfe_internal.h"
 
 #include <math.h>
@@ -40,6 +49,21 @@ __device__ __forceinline__ void st_coherent(int32_t *p, int v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ double ldd_coherent(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Blocks are dispatched round robin over the 8 XCDs; block b runs tile
+// (b % 8) * stride + b / 8, so each XCD works on a contiguous run of tiles
+// (neighbouring cells) and keeps their data in its own L2.  -1: no tile.
+__device__ __forceinline__ int tile_of_block(const Ctl &c)
+{
+    const int b = blockIdx.x;
+    const int t = (b & 7) * c.xcd_stride + (b >> 3);
+    return t < c.n_tiles ? t : -1;
+}
+
 template <typename R>
 __device__ __forceinline__ R powi_or_pow(R s, int ip, R p)
 {
@@ -51,18 +75,21 @@ __device__ __forceinline__ R powi_or_pow(R s, int ip, R p)
     return pow(s, p);
 }
 
-// Cell grid of a system for its current (strained) box: floor(L / rc) cells
-// per dimension, at least 1 and at most the capacity fixed at set-up.
-__device__ __forceinline__ void grid_of(const SysDesc &d, const SysState &st, double rc,
-                                        int nc[3], double box[3], double ibox[3])
+__device__ __forceinline__ void eff_box(const SysState &st, double box[3], double ibox[3])
 {
     for (int k = 0; k < 3; ++k) {
         box[k] = st.box[k] * st.pscale[k];
         ibox[k] = 1.0 / box[k];
-        int n = (int)floor(box[k] / rc);
+    }
+}
+
+// Cell grid for the list build: cells of at least rc + skin, capped.
+__device__ __forceinline__ void cell_grid(const SysDesc &d, const double box[3], double rl, int nc[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        int n = (int)floor(box[k] / rl);
         n = n < 1 ? 1 : n;
-        n = n > d.nc_max[k] ? d.nc_max[k] : n;
-        nc[k] = n;
+        nc[k] = n > d.nc_max[k] ? d.nc_max[k] : n;
     }
 }
 
@@ -72,8 +99,15 @@ __device__ __forceinline__ int cell_coord(double x, double ibox, int nc)
     s -= floor(s);
     int c = (int)(s * nc);
     c = c < 0 ? 0 : c;
-    c = c >= nc ? nc - 1 : c;
-    return c;
+    return c >= nc ? nc - 1 : c;
+}
+
+__device__ __forceinline__ int cell_of_pos(const double4 &x, const double ibox[3], const int nc[3])
+{
+    const int cx = cell_coord(x.x, ibox[0], nc[0]);
+    const int cy = cell_coord(x.y, ibox[1], nc[1]);
+    const int cz = cell_coord(x.z, ibox[2], nc[2]);
+    return (cz * nc[1] + cy) * nc[0] + cx;
 }
 
 __device__ __forceinline__ double min_image(double d, double box, double ibox)
@@ -121,16 +155,18 @@ __device__ __forceinline__ bool o_step_on(const SysDesc &d)
     return d.mode != MODE_FORCE && d.mode != MODE_NVE && d.tau_damp > 0.0 && d.T0 > 0.0;
 }
 
-// Total force on an atom at coupling lam: FL interpolates with the Einstein
-// reference (section 2.1), RS and dCCI scale the interaction (eq. H_RS).
-__device__ __forceinline__ double total_force(int mode, double lam, double fint, double x,
-                                              const double *x0, int64_t idx, double k)
+__device__ __forceinline__ bool scales_interaction(int mode)
 {
-    if (mode == MODE_FL) {
-        double fref = x0 ? -k * (x - x0[idx]) : 0.0;
-        return lam * fint + (1.0 - lam) * fref;
-    }
-    if (mode == MODE_RS || mode == MODE_DCCI_T || mode == MODE_DCCI_P) return lam * fint;
+    return mode == MODE_RS || mode == MODE_DCCI_T || mode == MODE_DCCI_P;
+}
+
+// Total force component at coupling lam: FL interpolates with the Einstein
+// reference (section 2.1), RS and dCCI scale the interaction (eq. H_RS).
+__device__ __forceinline__ double total_force(int mode, double lam, double fint, double x, double x0,
+                                              double k)
+{
+    if (mode == MODE_FL) return lam * fint + (1.0 - lam) * (-k * (x - x0));
+    if (scales_interaction(mode)) return lam * fint;
     return fint;
 }
 
@@ -144,6 +180,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double *out)
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double a = v[k];
+#pragma unroll
         for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
         if (lane == 0) red[wave][k] = a;
     }
@@ -155,234 +192,482 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double *out)
     }
 }
 
-// ------------------------------------------------------------ cell index ---
-__global__ void __launch_bounds__(256) k_assign_cells(Ctl c, DevPtrs p, double rc)
+__device__ __forceinline__ double block_max(double v)
 {
-    const Tile tile = p.tiles[blockIdx.x];
-    if ((int)threadIdx.x >= tile.count) return;
-    const SysDesc &d = p.desc[tile.sys];
-    const SysState &st = p.state[tile.sys];
-    int nc[3];
-    double box[3], ibox[3];
-    grid_of(d, st, rc, nc, box, ibox);
-    const int64_t i = tile.start + threadIdx.x, N = c.n_total;
-    int cc[3];
-    bool fin = true;
-    for (int k = 0; k < 3; ++k) {
-        double xk = p.x[k * N + i] * st.pscale[k];
-        fin = fin && isfinite(xk);
-        cc[k] = cell_coord(xk, ibox[k], nc[k]);
-    }
-    if (!fin) atomicOr(&p.state[tile.sys].err, ERR_NONFINITE);
-    p.cell_of[i] = (cc[2] * nc[1] + cc[1]) * nc[0] + cc[0];
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double m = 0.0;
+    for (int w = 0; w < nw; ++w) m = fmax(m, red[w]);
+    return m;
 }
 
-// ------------------------------------------------------------------ bin ----
-// One workgroup per system: zero counts, count, exclusive scan (cell starts
-// in global sorted positions), placement, then an insertion sort of every
-// cell's segment so that the order inside a cell is by atom index.
-__global__ void __launch_bounds__(kBinThreads) k_bin(Ctl c, DevPtrs p, double rc)
+// -------------------------------------------------------- gather/scatter ---
+__global__ void __launch_bounds__(256) k_iota(Ctl c, DevPtrs p)
 {
-    const int sys = blockIdx.x;
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    if ((int)threadIdx.x < tile.count) {
+        const int t = tile.start + threadIdx.x;
+        p.perm[t] = t;
+    }
+}
+
+// Caller arrays (original order, [3][N]) -> sorted internal arrays.
+__global__ void __launch_bounds__(256) k_gather(Ctl c, DevPtrs p, int with_f)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    if ((int)threadIdx.x >= tile.count) return;
+    const SysState &st = p.state[tile.sys];
+    const int64_t N = c.n_total;
+    const int t = tile.start + threadIdx.x;
+    const int i = p.perm[t];
+    p.xs[t] = make_double4(p.x[i] * st.pscale[0], p.x[N + i] * st.pscale[1], p.x[2 * N + i] * st.pscale[2], 0.0);
+    p.vs[t] = make_double4(p.v[i], p.v[N + i], p.v[2 * N + i], 0.0);
+    if (with_f) p.fs[t] = make_double4(p.f[i], p.f[N + i], p.f[2 * N + i], 0.0);
+    if (p.x0) p.x0s[t] = make_double4(p.x0[i], p.x0[N + i], p.x0[2 * N + i], 0.0);
+}
+
+// Sorted internal arrays -> caller arrays.  what: 1 x and v, 2 f, 4 e_atom,
+// 8 grad_x = -F grad_scale.
+__global__ void __launch_bounds__(256) k_scatter(Ctl c, DevPtrs p, int what)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    if ((int)threadIdx.x >= tile.count) return;
+    const int64_t N = c.n_total;
+    const int t = tile.start + threadIdx.x;
+    const int i = p.perm[t];
+    if (what & 1) {
+        const double4 x = p.xs[t], v = p.vs[t];
+        p.x[i] = x.x;
+        p.x[N + i] = x.y;
+        p.x[2 * N + i] = x.z;
+        p.v[i] = v.x;
+        p.v[N + i] = v.y;
+        p.v[2 * N + i] = v.z;
+    }
+    const double4 f = p.fs[t];
+    if (what & 2) {
+        p.f[i] = f.x;
+        p.f[N + i] = f.y;
+        p.f[2 * N + i] = f.z;
+    }
+    if ((what & 4) && p.e_atom) p.e_atom[i] = p.e_s[t];
+    if ((what & 8) && p.grad_x) {
+        const double g = p.grad_scale ? p.grad_scale[tile.sys] : 1.0;
+        p.grad_x[i] = -f.x * g;
+        p.grad_x[N + i] = -f.y * g;
+        p.grad_x[2 * N + i] = -f.z * g;
+    }
+}
+
+// ------------------------------------------------------------- integrate ---
+// Steps 3-6 of the switched step for one atom: B kick with F(lambda_{k+1}),
+// A half drift with isotropic box scaling, O Langevin step with zero-sum
+// noise, A half drift.  Then the displacement from the list-build position
+// (scaled with the box) for the rebuild test.
+__global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
     const SysDesc &d = p.desc[sys];
     const SysState &st = p.state[sys];
-    int nc3[3];
+    double dmax = 0.0;
+    if ((int)threadIdx.x < tile.count) {
+        const int t = tile.start + threadIdx.x;
+        double4 x = p.xs[t];
+        if (d.mode != MODE_FORCE) {
+            double4 v = p.vs[t];
+            const double4 f = p.fs[t];
+            const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
+            const double hdt = 0.5 * c.dt, ka = hdt * d.acc;
+            v.x = v.x * st.decay + ka * total_force(d.mode, st.lam, f.x, x.x, x0.x, d.k_spring) * st.phi;
+            v.y = v.y * st.decay + ka * total_force(d.mode, st.lam, f.y, x.y, x0.y, d.k_spring) * st.phi;
+            v.z = v.z * st.decay + ka * total_force(d.mode, st.lam, f.z, x.z, x0.z, d.k_spring) * st.phi;
+            x.x = x.x * st.grow + (v.x * hdt) * st.psi;
+            x.y = x.y * st.grow + (v.y * hdt) * st.psi;
+            x.z = x.z * st.grow + (v.z * hdt) * st.psi;
+            if (o_step_on(d)) {
+                double z[3];
+                normals3(c.seed, d.stream, (uint64_t)st.step, (uint64_t)(p.perm[t] - d.off), z);
+                const double c2s = d.c2 * d.sigv;
+                v.x = d.c1 * v.x + c2s * (z[0] - st.noise_mean[0]);
+                v.y = d.c1 * v.y + c2s * (z[1] - st.noise_mean[1]);
+                v.z = d.c1 * v.z + c2s * (z[2] - st.noise_mean[2]);
+            }
+            x.x = x.x * st.grow + (v.x * hdt) * st.psi;
+            x.y = x.y * st.grow + (v.y * hdt) * st.psi;
+            x.z = x.z * st.grow + (v.z * hdt) * st.psi;
+            p.xs[t] = x;
+            p.vs[t] = v;
+        }
+        if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z))) atomicOr(&p.state[sys].err, ERR_NONFINITE);
+        const double4 b = p.xb[t];
+        const double dx = x.x - b.x * (st.box[0] / st.box_build[0]);
+        const double dy = x.y - b.y * (st.box[1] / st.box_build[1]);
+        const double dz = x.z - b.z * (st.box[2] / st.box_build[2]);
+        dmax = dx * dx + dy * dy + dz * dz;
+        if (!(dmax == dmax)) dmax = 1e300;  // NaN forces a rebuild (and is flagged above)
+    }
+    dmax = block_max(dmax);
+    // non-negative doubles order like their bit patterns: one atomic max per
+    // block into this step's slot of the system
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(&p.disp_max[2 * sys + (st.step & 1)]),
+                  (unsigned long long)__double_as_longlong(dmax));
+}
+
+// --------------------------------------------------------------- rebuild ---
+// Does this system's Verlet list need a rebuild?  A pair now within rc that
+// is missing from the list was at least rc + skin apart at the build; after
+// box scaling by s and displacements of at most delta per atom it is at
+// least s (rc + skin) - 2 delta apart, so the list is still complete while
+// 2 delta + (1 - s)(rc + skin) <= skin.
+__device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, int sys)
+{
+    if (c.force_rebuild) return true;
+    const SysDesc &d = p.desc[sys];
+    const SysState &st = p.state[sys];
+    const double m = p.disp_max[2 * sys + (st.step & 1)];
+    double smin = 1e300;
+    for (int k = 0; k < 3; ++k) smin = fmin(smin, (st.box[k] * st.pscale[k]) / st.box_build[k]);
+    const double shrink = smin < 1.0 ? 1.0 - smin : 0.0;
+    return 2.0 * sqrt(m) + (sw.rc + d.skin) * shrink > d.skin;
+}
+
+__global__ void __launch_bounds__(256) k_rb_count(Ctl c, DevPtrs p, SwParams sw)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
+    const bool rb = list_stale(c, p, sw, sys);
+    if (threadIdx.x == 0) {
+        p.state[sys].rb = rb ? 1 : 0;
+        // clear the slot the next step's integrate fills (both on a forced build)
+        if (ti == p.desc[sys].tile_begin) {
+            const int64_t step = p.state[sys].step;
+            p.disp_max[2 * sys + ((step + 1) & 1)] = 0.0;
+            if (c.force_rebuild) p.disp_max[2 * sys + (step & 1)] = 0.0;
+        }
+    }
+    if (!rb || (int)threadIdx.x >= tile.count) return;
+    const SysDesc &d = p.desc[sys];
+    const SysState &st = p.state[sys];
     double box[3], ibox[3];
-    grid_of(d, st, rc, nc3, box, ibox);
+    int nc[3];
+    eff_box(st, box, ibox);
+    cell_grid(d, box, sw.rc + d.skin, nc);
+    const int t = tile.start + threadIdx.x;
+    const int cell = cell_of_pos(p.xs[t], ibox, nc);
+    p.cellid[t] = cell;
+    p.rank[t] = atomicAdd(&p.cell_count[d.cell_base + cell], 1);
+}
+
+// One workgroup per system: exclusive scan of the cell counts into cell
+// starts (sorted positions); the counts are cleared for the next build.
+__global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwParams sw)
+{
+    const int sys = blockIdx.x;
+    SysState &st = p.state[sys];
+    if (!st.rb) return;
+    const SysDesc &d = p.desc[sys];
+    double box[3], ibox[3];
+    int nc3[3];
+    eff_box(st, box, ibox);
+    cell_grid(d, box, sw.rc + d.skin, nc3);
     const int nc = nc3[0] * nc3[1] * nc3[2];
     int32_t *cnt = p.cell_count + d.cell_base;
-    int32_t *cur = p.cursor + d.cell_base;
-    int32_t *start = p.cell_start + d.cell_base + sys;  // nc + 1 entries per system
-    const int64_t off = d.off;
-    const int n = (int)d.n;
-    const int tid = threadIdx.x;
+    int32_t *start = p.cell_start + d.cell_base + sys;  // nc + 1 entries
+    const int off = (int)d.off, n = (int)d.n, tid = threadIdx.x;
 
-    for (int q = tid; q < nc; q += kBinThreads) cnt[q] = 0;
-    __threadfence();
-    __syncthreads();
-    for (int i = tid; i < n; i += kBinThreads) atomicAdd(&cnt[p.cell_of[off + i]], 1);
-    __threadfence();
-    __syncthreads();
-
-    __shared__ int32_t part[kBinThreads];
-    const int per = (nc + kBinThreads - 1) / kBinThreads;
-    const int lo = tid * per, hi = min(lo + per, nc);
+    __shared__ int32_t part[kSortThreads];
+    const int per = (nc + kSortThreads - 1) / kSortThreads;
+    const int lo = min(tid * per, nc), hi = min(lo + per, nc);
     int sum = 0;
-    for (int q = lo; q < hi; ++q) sum += ld_coherent(&cnt[q]);
+    for (int q = lo; q < hi; ++q) sum += cnt[q];
     part[tid] = sum;
     __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 partial sums
-    for (int o = 1; o < kBinThreads; o <<= 1) {
-        int add = tid >= o ? part[tid - o] : 0;
+    for (int o = 1; o < kSortThreads; o <<= 1) {
+        const int add = tid >= o ? part[tid - o] : 0;
         __syncthreads();
         part[tid] += add;
         __syncthreads();
     }
-    int run = (int)off + part[tid] - sum;
+    int run = off + part[tid] - sum;
     for (int q = lo; q < hi; ++q) {
         start[q] = run;
-        cur[q] = run;
-        run += ld_coherent(&cnt[q]);
+        run += cnt[q];
+        cnt[q] = 0;
     }
-    if (tid == 0) start[nc] = (int)off + n;
-    __threadfence();
-    __syncthreads();
-    for (int i = tid; i < n; i += kBinThreads) {
-        int slot = atomicAdd(&cur[p.cell_of[off + i]], 1);
-        p.sorted[slot] = (int32_t)(off + i);
-    }
-    __threadfence();
-    __syncthreads();
-    for (int q = tid; q < nc; q += kBinThreads) {
-        const int b = ld_coherent(&start[q]), e = ld_coherent(&start[q + 1]);
-        for (int a = b + 1; a < e; ++a) {
-            int key = ld_coherent(&p.sorted[a]);
-            int m = a - 1;
-            while (m >= b) {
-                int w = ld_coherent(&p.sorted[m]);
-                if (w <= key) break;
-                st_coherent(&p.sorted[m + 1], w);
-                --m;
-            }
-            st_coherent(&p.sorted[m + 1], key);
-        }
+    if (tid == 0) {
+        start[nc] = off + n;
+        for (int k = 0; k < 3; ++k) st.box_build[k] = box[k];
+        st.n_rebuild += 1;
     }
 }
 
+// Atom data into its cell's segment of the staging arrays (slot by rank, so
+// the order inside a cell is not yet fixed).
+__global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
+    if (!p.state[sys].rb || (int)threadIdx.x >= tile.count) return;
+    const SysDesc &d = p.desc[sys];
+    const int t = tile.start + threadIdx.x;
+    const int cell = p.cellid[t];
+    const int s = p.cell_start[d.cell_base + sys + cell] + p.rank[t];
+    p.txs[s] = p.xs[t];
+    p.tvs[s] = p.vs[t];
+    p.tfs[s] = p.fs[t];
+    if (p.x0) p.tx0s[s] = p.x0s[t];
+    p.tperm[s] = p.perm[t];
+    p.norder[s] = cell;
+}
+
+// Final order: inside a cell atoms follow the caller's atom index.  Each
+// staged atom counts the smaller indices of its cell and moves there.
+__global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
+    if (!p.state[sys].rb || (int)threadIdx.x >= tile.count) return;
+    const SysDesc &d = p.desc[sys];
+    const int i = tile.start + threadIdx.x;
+    const int cell = p.norder[i];
+    const int32_t *start = p.cell_start + d.cell_base + sys;
+    const int b = start[cell], e = start[cell + 1];
+    const int key = p.tperm[i];
+    int rank = 0;
+    for (int j = b; j < e; ++j) rank += p.tperm[j] < key ? 1 : 0;
+    const int s = b + rank;
+    const double4 x = p.txs[i];
+    p.xs[s] = x;
+    p.xb[s] = x;
+    p.vs[s] = p.tvs[i];
+    p.fs[s] = p.tfs[i];
+    if (p.x0) p.x0s[s] = p.tx0s[i];
+    p.perm[s] = key;
+}
+
+// Verlet list of sorted positions within rc + skin from the (up to) 27 cells
+// around the atom's cell (fewer when a dimension has fewer than 3 cells, so
+// that no cell is visited twice).  32 lanes per atom, one per stencil cell:
+// each lane marks the candidates of its cell, a prefix sum over the lanes
+// gives every cell its slot range, so the list is in stencil-cell order and,
+// inside a cell, in sorted order.  Blocks of 256 threads hold 8 atoms; S
+// blocks cover one tile.
+__global__ void __launch_bounds__(256) k_rb_list(Ctl c, DevPtrs p, SwParams sw, int S)
+{
+    const int nv = c.n_tiles * S;
+    const int v = (blockIdx.x & 7) * ((nv + 7) / 8) + (blockIdx.x >> 3);
+    if (v >= nv) return;
+    const int ti = v / S, sub = v % S;
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
+    if (!p.state[sys].rb) return;
+    const int a_loc = sub * 8 + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31;
+    const bool valid = a_loc < tile.count;
+    const SysDesc &d = p.desc[sys];
+    const SysState &st = p.state[sys];
+    double box[3], ibox[3];
+    int nc[3];
+    eff_box(st, box, ibox);
+    const double rl = sw.rc + d.skin, rl2 = rl * rl;
+    cell_grid(d, box, rl, nc);
+    const int64_t N = c.n_total;
+    const int s = tile.start + (valid ? a_loc : 0);
+    const double4 xi = p.xs[s];
+    const int ci = cell_of_pos(xi, ibox, nc);
+    const int cx = ci % nc[0], cy = (ci / nc[0]) % nc[1], cz = ci / (nc[0] * nc[1]);
+    const int nxo = nc[0] >= 3 ? 3 : nc[0], nyo = nc[1] >= 3 ? 3 : nc[1], nzo = nc[2] >= 3 ? 3 : nc[2];
+    const int x0c = nc[0] >= 3 ? cx - 1 : 0, y0c = nc[1] >= 3 ? cy - 1 : 0, z0c = nc[2] >= 3 ? cz - 1 : 0;
+    const int32_t *start = p.cell_start + d.cell_base + sys;
+    const int ncell = nxo * nyo * nzo;
+    unsigned long long mask = 0;
+    int b = 0, cnt = 0;
+    bool over = false;
+    if (valid && lane < ncell) {
+        const int ox = lane % nxo, oy = (lane / nxo) % nyo, oz = lane / (nxo * nyo);
+        int xx = x0c + ox, yy = y0c + oy, zz = z0c + oz;
+        xx = xx < 0 ? xx + nc[0] : (xx >= nc[0] ? xx - nc[0] : xx);
+        yy = yy < 0 ? yy + nc[1] : (yy >= nc[1] ? yy - nc[1] : yy);
+        zz = zz < 0 ? zz + nc[2] : (zz >= nc[2] ? zz - nc[2] : zz);
+        const int cell = (zz * nc[1] + yy) * nc[0] + xx;
+        b = start[cell];
+        const int e = start[cell + 1];
+        over = e - b > 64;
+        const int eb = over ? b + 64 : e;
+        for (int j = b; j < eb; ++j) {
+            if (j == s) continue;
+            const double4 xj = p.xs[j];
+            const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
+            const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
+            const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
+            if (dx * dx + dy * dy + dz * dz < rl2) mask |= 1ull << (j - b);
+        }
+        cnt = __popcll(mask);
+    }
+    // exclusive prefix of the per-cell counts over the 32 lanes of this atom
+    int incl = cnt;
+    for (int o = 1; o < 32; o <<= 1) {
+        const int u = __shfl_up(incl, o, 32);
+        if (lane >= o) incl += u;
+    }
+    const int total = __shfl(incl, 31, 32);
+    int slot = incl - cnt;
+    while (mask) {
+        const int k = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        if (slot < kMaxList) p.nl[(int64_t)slot * N + s] = b + k;
+        ++slot;
+    }
+    if (!valid) return;
+    if (over || total > kMaxList) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
+    if (lane == 0) p.nl_cnt[s] = total < kMaxList ? total : kMaxList;
+}
+
 // ---------------------------------------------------------------- pass 1 ---
-// Neighbour search over the (up to) 27 cells around the atom's cell, pair
-// terms (energy, force, virial, parameter derivative: half per ordered pair)
-// and three-body moments.  R is the arithmetic type of the terms.
+// Pair terms (energy, force, virial, parameter derivative: half per ordered
+// pair), the three-body moments and the atom's own three-body energy.  R is
+// the arithmetic type of the terms; sums are FP64.
 template <typename R>
+struct alignas(16) Mom {
+    R v[12];
+};
+
+template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 {
-    constexpr int NV = 19;  // E, virial 9, dtheta 9
+    constexpr int NV = 20;  // E2, virial 9, dtheta 9, E3
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-
-    const Tile tile = p.tiles[blockIdx.x];
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
     const int sys = tile.sys;
-    const SysDesc &d = p.desc[sys];
     const SysState &st = p.state[sys];
     const int64_t N = c.n_total;
-    const bool grad = (c.flags & 1) != 0;
 
     if ((int)threadIdx.x < tile.count) {
-        int nc[3];
         double box[3], ibox[3];
-        grid_of(d, st, sw.rc, nc, box, ibox);
-        const int64_t t = tile.start + threadIdx.x;
-        const int i = p.sorted[t];
-        const double ps0 = st.pscale[0], ps1 = st.pscale[1], ps2 = st.pscale[2];
-        const double xi = p.x[i] * ps0, yi = p.x[N + i] * ps1, zi = p.x[2 * N + i] * ps2;
-        const int ci = p.cell_of[i];
-        const int cx = ci % nc[0], cy = (ci / nc[0]) % nc[1], cz = ci / (nc[0] * nc[1]);
-        const int nxo = nc[0] >= 3 ? 3 : nc[0], nyo = nc[1] >= 3 ? 3 : nc[1],
-                  nzo = nc[2] >= 3 ? 3 : nc[2];
-        const int x0c = nc[0] >= 3 ? cx - 1 : 0, y0c = nc[1] >= 3 ? cy - 1 : 0,
-                  z0c = nc[2] >= 3 ? cz - 1 : 0;
-        const int32_t *start = p.cell_start + d.cell_base + sys;
-
+        eff_box(st, box, ibox);
+        const int t = tile.start + threadIdx.x;
+        const double4 xi = p.xs[t];
+        const int cnt = p.nl_cnt[t];
         const R rc = (R)sw.rc, sig = (R)sw.sig, eA = (R)sw.eA, B = (R)sw.B, pp = (R)sw.p,
-                qq = (R)sw.q, gam = (R)sw.gam;
-        double m_s = 0, m_q = 0, m_v[3] = {0, 0, 0}, m_M[6] = {0, 0, 0, 0, 0, 0};
-        double F2[3] = {0, 0, 0};
-        int nn = 0;
-
-        for (int oz = 0; oz < nzo; ++oz) {
-            int zz = z0c + oz;
-            zz = zz < 0 ? zz + nc[2] : (zz >= nc[2] ? zz - nc[2] : zz);
-            for (int oy = 0; oy < nyo; ++oy) {
-                int yy = y0c + oy;
-                yy = yy < 0 ? yy + nc[1] : (yy >= nc[1] ? yy - nc[1] : yy);
-                for (int ox = 0; ox < nxo; ++ox) {
-                    int xx = x0c + ox;
-                    xx = xx < 0 ? xx + nc[0] : (xx >= nc[0] ? xx - nc[0] : xx);
-                    const int cell = (zz * nc[1] + yy) * nc[0] + xx;
-                    const int b = start[cell], e = start[cell + 1];
-                    for (int s = b; s < e; ++s) {
-                        const int j = p.sorted[s];
-                        if (j == i) continue;
-                        double dx = min_image(p.x[j] * ps0 - xi, box[0], ibox[0]);
-                        double dy = min_image(p.x[N + j] * ps1 - yi, box[1], ibox[1]);
-                        double dz = min_image(p.x[2 * N + j] * ps2 - zi, box[2], ibox[2]);
-                        double r2d = dx * dx + dy * dy + dz * dz;
-                        if (r2d >= sw.rc2) continue;
-                        if (nn < kMaxNb) p.nbr[(int64_t)nn * N + t] = j;
-                        ++nn;
-                        const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
-                        const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-                        const R ri = R(1) / r;
-                        const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
-                        // Inside the cutoff in FP64 may round to r >= rc in the
-                        // term precision; the terms vanish there, so zero them.
-                        const R den = r - rc;
-                        const bool in = den < R(0);
-                        const R di = in ? R(1) / den : R(0);
-                        const R sr = sig * ri;
-                        const R sp = powi_or_pow(sr, sw.ip, pp);
-                        const R sq = powi_or_pow(sr, sw.iq, qq);
-                        const R ex = in ? exp(sig * di) : R(0);
-                        const R br = B * sp - sq;
-                        const R phi = eA * br * ex;
-                        const R dphi = eA * ex * ((qq * sq - pp * B * sp) * ri - br * sig * di * di);
-                        const R g = in ? exp(gam * sig * di) : R(0);
-                        // moments
-                        m_s += (double)g;
-                        m_q += (double)(g * g);
-                        m_v[0] += (double)(g * ux);
-                        m_v[1] += (double)(g * uy);
-                        m_v[2] += (double)(g * uz);
-                        m_M[0] += (double)(g * ux * ux);
-                        m_M[1] += (double)(g * uy * uy);
-                        m_M[2] += (double)(g * uz * uz);
-                        m_M[3] += (double)(g * ux * uy);
-                        m_M[4] += (double)(g * ux * uz);
-                        m_M[5] += (double)(g * uy * uz);
-                        // pair: F_i += phi2'(r) u_ij ; E_i += phi2/2 ; virial half
-                        F2[0] += (double)(dphi * ux);
-                        F2[1] += (double)(dphi * uy);
-                        F2[2] += (double)(dphi * uz);
-                        acc[0] += 0.5 * (double)phi;
-                        const R hv = R(0.5) * dphi * r;
-                        const R uu[3] = {ux, uy, uz};
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-#pragma unroll
-                            for (int bb = 0; bb < 3; ++bb) acc[1 + 3 * a + bb] += (double)(hv * uu[a] * uu[bb]);
-                        if (grad) {
-                            const R lns = log(sr);
-                            acc[10] += 0.5 * (double)((R)sw.eps * br * ex);                  // A
-                            acc[11] += 0.5 * (double)(eA * sp * ex);                         // B
-                            acc[12] += 0.5 * (double)(eA * B * sp * lns * ex);               // p
-                            acc[13] += 0.5 * (double)(-eA * sq * lns * ex);                  // q
-                            acc[14] += 0.5 * (double)(phi * sig * sig * di * di);            // a
-                            acc[17] += 0.5 * (double)(eA * ex * ((pp * B * sp - qq * sq) / sig + br * r * di * di));  // sigma
-                            acc[18] += 0.5 * (double)((R)sw.A * br * ex);                    // epsilon
-                        }
-                    }
-                }
+                qq = (R)sw.q, gsig = (R)(sw.gam * sw.sig);
+        double m[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double F2x = 0, F2y = 0, F2z = 0;
+        double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
+        int nin = 0;
+        for (int k = 0; k < cnt; ++k) {
+            const int j = p.nl[(int64_t)k * N + t];
+            const double4 xj = p.xs[j];
+            const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
+            const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
+            const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
+            if (dx * dx + dy * dy + dz * dz >= sw.rc2) continue;
+            ++nin;
+            const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
+            const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            const R ri = R(1) / r;
+            const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
+            // inside the cutoff in FP64 may round to r >= rc in the term
+            // precision; the terms vanish there, so they are zeroed
+            const R den = r - rc;
+            const bool in = den < R(0);
+            const R di = in ? R(1) / den : R(0);
+            const R sr = sig * ri;
+            const R sp = powi_or_pow(sr, sw.ip, pp);
+            const R sq = powi_or_pow(sr, sw.iq, qq);
+            const R ex = in ? exp(sig * di) : R(0);
+            const R br = B * sp - sq;
+            const R phi = eA * br * ex;
+            const R dphi = eA * ex * ((qq * sq - pp * B * sp) * ri - br * sig * di * di);
+            const R g = in ? exp(gsig * di) : R(0);
+            const R gx = g * ux, gy = g * uy, gz = g * uz;
+            m[0] += (double)g;
+            m[1] += (double)(g * g);
+            m[2] += (double)gx;
+            m[3] += (double)gy;
+            m[4] += (double)gz;
+            m[5] += (double)(gx * ux);
+            m[6] += (double)(gy * uy);
+            m[7] += (double)(gz * uz);
+            m[8] += (double)(gx * uy);
+            m[9] += (double)(gx * uz);
+            m[10] += (double)(gy * uz);
+            // F_i += phi2'(r) u_ij ; E_i += phi2/2 ; virial, half per ordered pair
+            const R fx = dphi * ux, fy = dphi * uy, fz = dphi * uz;
+            F2x += (double)fx;
+            F2y += (double)fy;
+            F2z += (double)fz;
+            acc[0] += 0.5 * (double)phi;
+            const R hr = R(0.5) * r;
+            vxx += (double)(hr * fx * ux);
+            vyy += (double)(hr * fy * uy);
+            vzz += (double)(hr * fz * uz);
+            vxy += (double)(hr * fx * uy);
+            vxz += (double)(hr * fx * uz);
+            vyz += (double)(hr * fy * uz);
+            if (GRAD) {
+                const R lns = log(sr);
+                acc[10] += 0.5 * (double)((R)sw.eps * br * ex);                   // A
+                acc[11] += 0.5 * (double)(eA * sp * ex);                          // B
+                acc[12] += 0.5 * (double)(eA * B * sp * lns * ex);                // p
+                acc[13] += 0.5 * (double)(-eA * sq * lns * ex);                   // q
+                acc[14] += 0.5 * (double)(phi * sig * sig * di * di);             // a
+                acc[17] += 0.5 * (double)(eA * ex * ((pp * B * sp - qq * sq) / sig + br * r * di * di));  // sigma
+                acc[18] += 0.5 * (double)((R)sw.A * br * ex);                     // epsilon
             }
         }
-        if (nn > kMaxNb) {
-            atomicOr(&p.state[sys].err, ERR_OVERFLOW);
-            nn = kMaxNb;
+        acc[1] = vxx;
+        acc[2] = vxy;
+        acc[3] = vxz;
+        acc[4] = vxy;
+        acc[5] = vyy;
+        acc[6] = vyz;
+        acc[7] = vxz;
+        acc[8] = vyz;
+        acc[9] = vzz;
+        // own three-body energy from the FP64 moments
+        const double c0 = sw.cos0, omc = 1.0 - c0;
+        const double MF = m[5] * m[5] + m[6] * m[6] + m[7] * m[7] + 2.0 * (m[8] * m[8] + m[9] * m[9] + m[10] * m[10]);
+        const double vv = m[2] * m[2] + m[3] * m[3] + m[4] * m[4];
+        const double Phi = MF - 2.0 * c0 * vv + c0 * c0 * m[0] * m[0] - omc * omc * m[1];
+        acc[19] = 0.5 * sw.le * Phi;
+        if (GRAD) {
+            acc[15] = 0.5 * sw.eps * Phi;  // lambda_sw
+            acc[18] += 0.5 * sw.lam * Phi; // epsilon (three-body part)
         }
-        p.nnb[t] = nn;
-        p.mom[0 * N + i] = m_s;
-        p.mom[1 * N + i] = m_q;
-        p.mom[2 * N + i] = m_v[0];
-        p.mom[3 * N + i] = m_v[1];
-        p.mom[4 * N + i] = m_v[2];
+        Mom<R> mo;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) p.mom[(5 + k) * N + i] = m_M[k];
-        p.f[i] = F2[0];
-        p.f[N + i] = F2[1];
-        p.f[2 * N + i] = F2[2];
-        if (p.e_atom) p.e_atom[i] = acc[0];
+        for (int k = 0; k < 11; ++k) mo.v[k] = (R)m[k];
+        mo.v[11] = R(0);
+        reinterpret_cast<Mom<R> *>(p.mom)[t] = mo;
+        p.nnb[t] = nin;
+        p.fs[t] = make_double4(F2x, F2y, F2z, 0.0);
+        p.e_s[t] = acc[0] + acc[19];
     }
-    block_reduce<NV>(acc, p.part1 + (int64_t)blockIdx.x * kNumPart);
+    block_reduce<NV>(acc, p.part1 + (int64_t)ti * kNumPart);
 }
 
 // ---------------------------------------------------------------- pass 2 ---
@@ -391,8 +676,8 @@ __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 //   (le/2) [ dg H u + (4 g / r) ((M u - (u.M.u) u) - c0 (v - (v.u) u)) ],
 //   H = 2 u.M.u - 4 c0 v.u + 2 c0^2 s - 2 (1 - c0)^2 g.
 template <typename R>
-__device__ __forceinline__ void d_e3(const R mom[11], R ux, R uy, R uz, R g, R dg, R ri, R c0,
-                                     R hle, R out[3], R &H)
+__device__ __forceinline__ void d_e3(const R *mom, R ux, R uy, R uz, R g, R dg, R ri, R c0, R hle,
+                                     R out[3], R &H)
 {
     const R s = mom[0], vx = mom[2], vy = mom[3], vz = mom[4];
     const R Mxx = mom[5], Myy = mom[6], Mzz = mom[7], Mxy = mom[8], Mxz = mom[9], Myz = mom[10];
@@ -410,198 +695,13 @@ __device__ __forceinline__ void d_e3(const R mom[11], R ux, R uy, R uz, R g, R d
     out[2] = hle * (a * uz + b * ((muz - umu * uz) - c0 * (vz - vu * uz)));
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
-{
-    constexpr int NV = 24;  // E3, virial 9, dtheta 9, U_ref, K, noise 3
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-
-    const Tile tile = p.tiles[blockIdx.x];
-    const int sys = tile.sys;
-    const SysDesc &d = p.desc[sys];
-    const SysState &st = p.state[sys];
-    const int64_t N = c.n_total;
-    const bool grad = (c.flags & 1) != 0;
-
-    if ((int)threadIdx.x < tile.count) {
-        int nc[3];
-        double box[3], ibox[3];
-        grid_of(d, st, sw.rc, nc, box, ibox);
-        const int64_t t = tile.start + threadIdx.x;
-        const int a = p.sorted[t];
-        const double ps0 = st.pscale[0], ps1 = st.pscale[1], ps2 = st.pscale[2];
-        const double xa = p.x[a] * ps0, ya = p.x[N + a] * ps1, za = p.x[2 * N + a] * ps2;
-        double momA_d[11];
-#pragma unroll
-        for (int k = 0; k < 11; ++k) momA_d[k] = p.mom[k * N + a];
-        R momA[11];
-#pragma unroll
-        for (int k = 0; k < 11; ++k) momA[k] = (R)momA_d[k];
-        const R rc = (R)sw.rc, sig = (R)sw.sig, gam = (R)sw.gam, c0 = (R)sw.cos0;
-        const R hle = (R)(0.5 * sw.le);
-        double F3[3] = {0, 0, 0};
-        double gg = 0, ga = 0, gs = 0;  // sum H g dln g/d(gamma, a, sigma)
-        const int nn = p.nnb[t];
-        for (int k = 0; k < nn; ++k) {
-            const int j = p.nbr[(int64_t)k * N + t];
-            const double dx = min_image(p.x[j] * ps0 - xa, box[0], ibox[0]);
-            const double dy = min_image(p.x[N + j] * ps1 - ya, box[1], ibox[1]);
-            const double dz = min_image(p.x[2 * N + j] * ps2 - za, box[2], ibox[2]);
-            const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
-            const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            const R ri = R(1) / r;
-            const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
-            const R den = r - rc;
-            const bool in = den < R(0);
-            const R di = in ? R(1) / den : R(0);
-            const R g = in ? exp(gam * sig * di) : R(0);
-            const R dg = -g * gam * sig * di * di;
-            R momJ[11];
-#pragma unroll
-            for (int m = 0; m < 11; ++m) momJ[m] = (R)p.mom[m * N + j];
-            R tA[3], tJ[3], HA, HJ;
-            d_e3<R>(momA, ux, uy, uz, g, dg, ri, c0, hle, tA, HA);
-            d_e3<R>(momJ, -ux, -uy, -uz, g, dg, ri, c0, hle, tJ, HJ);
-            F3[0] += (double)tA[0] - (double)tJ[0];
-            F3[1] += (double)tA[1] - (double)tJ[1];
-            F3[2] += (double)tA[2] - (double)tJ[2];
-            const R dd[3] = {ddx, ddy, ddz};
-#pragma unroll
-            for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb) acc[1 + 3 * aa + bb] += (double)(tA[aa] * dd[bb]);
-            if (grad) {
-                const R hg = HA * g;
-                gg += (double)(hg * sig * di);
-                ga += (double)(hg * gam * sig * sig * di * di);
-                gs += (double)(hg * gam * r * di * di);
-            }
-        }
-        // own three-body energy from the FP64 moments
-        {
-            const double *m = momA_d;
-            const double c0d = sw.cos0, omc = 1.0 - c0d;
-            const double MF = m[5] * m[5] + m[6] * m[6] + m[7] * m[7] +
-                              2.0 * (m[8] * m[8] + m[9] * m[9] + m[10] * m[10]);
-            const double vv = m[2] * m[2] + m[3] * m[3] + m[4] * m[4];
-            const double Phi = MF - 2.0 * c0d * vv + c0d * c0d * m[0] * m[0] - omc * omc * m[1];
-            acc[0] = 0.5 * sw.le * Phi;
-            if (grad) {
-                const double hle_d = 0.5 * sw.le;
-                acc[10 + 4] = hle_d * ga;                 // a
-                acc[10 + 5] = 0.5 * sw.eps * Phi;         // lambda_sw
-                acc[10 + 6] = hle_d * gg;                 // gamma
-                acc[10 + 7] = hle_d * gs;                 // sigma
-                acc[10 + 8] = 0.5 * sw.lam * Phi;         // epsilon
-            }
-        }
-        if (p.e_atom) p.e_atom[a] += acc[0];
-        double F[3];
-        F[0] = p.f[a] + F3[0];
-        F[1] = p.f[N + a] + F3[1];
-        F[2] = p.f[2 * N + a] + F3[2];
-        p.f[a] = F[0];
-        p.f[N + a] = F[1];
-        p.f[2 * N + a] = F[2];
-        if (p.grad_x) {
-            const double gsc = p.grad_scale ? p.grad_scale[sys] : 1.0;
-            p.grad_x[a] = -F[0] * gsc;
-            p.grad_x[N + a] = -F[1] * gsc;
-            p.grad_x[2 * N + a] = -F[2] * gsc;
-        }
-        // Einstein reference (Frenkel-Ladd systems)
-        const bool fl = d.mode == MODE_FL && p.x0 != nullptr;
-        if (fl) {
-            double u = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                double dd = p.x[k * N + a] - p.x0[k * N + a];
-                u += dd * dd;
-            }
-            acc[19] = 0.5 * d.k_spring * u;
-        }
-        // final half kick of a dynamics step, then the kinetic energy
-        double vsq = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            double vk = p.v[k * N + a];
-            if (c.in_step && d.mode != MODE_FORCE) {
-                double ft = total_force(d.mode, st.lam, F[k], p.x[k * N + a], p.x0, k * N + a,
-                                        d.k_spring);
-                vk = vk * st.decay + ((0.5 * c.dt) * d.acc) * ft * st.phi;
-                p.v[k * N + a] = vk;
-            }
-            vsq += vk * vk;
-        }
-        acc[20] = d.mvv2e_m * vsq;
-        // normals of the next O step, for its zero-sum correction
-        if (o_step_on(d)) {
-            double z[3];
-            normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)(a - d.off), z);
-            acc[21] = z[0];
-            acc[22] = z[1];
-            acc[23] = z[2];
-        }
-    }
-    block_reduce<NV>(acc, p.part2 + (int64_t)blockIdx.x * kNumPart);
-}
-
-// ------------------------------------------------------------- integrate ---
-// Steps 3-6 of the switched step for one atom: B kick with F(lambda_{k+1}),
-// A half drift with isotropic box scaling, O Langevin step with zero-sum
-// noise, A half drift; then the cell index in the new box.
-__global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, double rc)
-{
-    const Tile tile = p.tiles[blockIdx.x];
-    if ((int)threadIdx.x >= tile.count) return;
-    const int sys = tile.sys;
-    const SysDesc &d = p.desc[sys];
-    const SysState &st = p.state[sys];
-    const int64_t i = tile.start + threadIdx.x, N = c.n_total;
-    int nc[3];
-    double box[3], ibox[3];
-    grid_of(d, st, rc, nc, box, ibox);
-    double x[3], v[3];
-    for (int k = 0; k < 3; ++k) {
-        x[k] = p.x[k * N + i];
-        v[k] = p.v[k * N + i];
-    }
-    if (d.mode != MODE_FORCE) {
-        const double hdt = 0.5 * c.dt;
-        for (int k = 0; k < 3; ++k) {
-            double ft = total_force(d.mode, st.lam, p.f[k * N + i], x[k], p.x0, k * N + i, d.k_spring);
-            v[k] = v[k] * st.decay + (hdt * d.acc) * ft * st.phi;
-        }
-        for (int k = 0; k < 3; ++k) x[k] = x[k] * st.grow + (v[k] * hdt) * st.psi;
-        if (o_step_on(d)) {
-            double z[3];
-            normals3(c.seed, d.stream, (uint64_t)st.step, (uint64_t)(i - d.off), z);
-            const double c2s = d.c2 * d.sigv;
-            for (int k = 0; k < 3; ++k) v[k] = d.c1 * v[k] + c2s * (z[k] - st.noise_mean[k]);
-        }
-        for (int k = 0; k < 3; ++k) x[k] = x[k] * st.grow + (v[k] * hdt) * st.psi;
-        for (int k = 0; k < 3; ++k) {
-            p.x[k * N + i] = x[k];
-            p.v[k * N + i] = v[k];
-        }
-    }
-    int cc[3];
-    bool fin = true;
-    for (int k = 0; k < 3; ++k) {
-        fin = fin && isfinite(x[k]);
-        cc[k] = cell_coord(x[k], ibox[k], nc[k]);
-    }
-    if (!fin) atomicOr(&p.state[sys].err, ERR_NONFINITE);
-    p.cell_of[i] = (cc[2] * nc[1] + cc[1]) * nc[0] + cc[0];
-}
-
-// -------------------------------------------------------------- finalize ---
+// ---- per-group reduction and scalar update (last tile of a group) --------
 constexpr double kGpaPerEvA3 = 1.602176634e-19 / 1e-30 / 1e9;
 
 __device__ double progress(const SysDesc &d, int64_t k)
 {
     if (d.s_steps <= 0) return 1.0;
-    int64_t kk = k < d.s_steps ? k : d.s_steps;
+    const int64_t kk = k < d.s_steps ? k : d.s_steps;
     return (double)kk / (double)d.s_steps;
 }
 
@@ -627,15 +727,15 @@ __device__ void baro_half(const SysDesc &d, SysState &st, double dt)
 {
     if (d.p_damp <= 0.0 || d.mode == MODE_FORCE) return;
     double tr = st.vir[0] + st.vir[4] + st.vir[8];
-    if (d.mode == MODE_RS || d.mode == MODE_DCCI_T || d.mode == MODE_DCCI_P) tr = st.lam * tr;
-    double g = d.alpha * 2.0 * st.K - tr - 3.0 * st.V * st.Ps;
+    if (scales_interaction(d.mode)) tr = st.lam * tr;
+    const double g = d.alpha * 2.0 * st.K - tr - 3.0 * st.V * st.Ps;
     st.veps += 0.5 * dt * g / d.wpiston;
 }
 
 // dCCI coupling (section 3): next (lambda, P_S) of a pair from instantaneous
 // per-atom energy and volume differences; returns false when singular.
-__device__ bool dcci_next(const SysDesc &dI, const SysState &I, const SysDesc &dII,
-                          const SysState &II, double &lam_new, double &Ps_new)
+__device__ bool dcci_next(const SysDesc &dI, const SysState &I, const SysDesc &dII, const SysState &II,
+                          double &lam_new, double &Ps_new)
 {
     const double du = I.U_int / (double)dI.n - II.U_int / (double)dII.n;
     const double dv = I.V / (double)dI.n - II.V / (double)dII.n;
@@ -703,112 +803,237 @@ __device__ void step_factors(const SysDesc &d, SysState &st, double dt, double r
         if (!(st.box[k] >= 2.0 * rc)) st.err |= ERR_BOX;
 }
 
-__global__ void __launch_bounds__(kFinThreads) k_finalize(Ctl c, DevPtrs p, SwParams sw, int mode,
-                                                            int log_every, int log_cap)
+// Start of a step for a group: switch (1), barostat half step (2), factors.
+__device__ void group_start_step(const Ctl &c, const DevPtrs &p, const SwParams &sw, const Group &G)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kFinThreads / 64;
-    // ---- phase A: per-system sums over tiles, fixed order ----------------
-    for (int s = wave; s < c.n_sys; s += nw) {
-        const SysDesc &d = p.desc[s];
-        SysState &st = p.state[s];
-        double sum1[kNumPart], sum2[kNumPart];
-        for (int k = 0; k < kNumPart; ++k) sum1[k] = sum2[k] = 0.0;
-        for (int t = d.tile_begin + lane; t < d.tile_end; t += 64) {
-            const double *a = p.part1 + (int64_t)t * kNumPart;
-            const double *b = p.part2 + (int64_t)t * kNumPart;
-            for (int k = 0; k < 19; ++k) sum1[k] += a[k];
-            for (int k = 0; k < kNumPart; ++k) sum2[k] += b[k];
+    const SysDesc &d0 = p.desc[G.s0];
+    SysState &s0 = p.state[G.s0];
+    double lam[2], Ps[2];
+    if (G.s1 >= 0) {
+        double l, P;
+        if (!dcci_next(d0, s0, p.desc[G.s1], p.state[G.s1], l, P)) {
+            s0.err |= ERR_DCCI;
+            p.state[G.s1].err |= ERR_DCCI;
         }
-        for (int k = 0; k < kNumPart; ++k) {
-            for (int off = 32; off > 0; off >>= 1) {
-                sum1[k] += __shfl_down(sum1[k], off, 64);
-                sum2[k] += __shfl_down(sum2[k], off, 64);
-            }
-        }
-        if (lane == 0) {
-            st.E2 = sum1[P_E];
-            st.E3 = sum2[P_E];
-            st.U_int = st.E2 + st.E3;
-            for (int k = 0; k < 9; ++k) st.vir[k] = sum1[P_VIR + k] + sum2[P_VIR + k];
-            for (int k = 0; k < 9; ++k) st.dth[k] = sum1[P_DTH + k] + sum2[P_DTH + k];
-            st.U_ref = sum2[P_UREF];
-            st.K = sum2[P_K];
-            for (int k = 0; k < 3; ++k) st.noise_mean[k] = sum2[P_NOISE + k] / (double)d.n;
-            st.V = st.box[0] * st.box[1] * st.box[2];
-            if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
-                st.err |= ERR_NONFINITE;
-            if (p.out) {
-                // dE/dstrain at diagonal strain e: Xi' (I + e)^-T
-                const double gsc = p.grad_scale ? p.grad_scale[s] : 1.0;
-                double *o = p.out + (int64_t)s * 20;
-                o[0] = st.U_int;
-                o[1] = st.U_ref;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) o[2 + 3 * a + b] = st.vir[3 * a + b] / st.pscale[b] * gsc;
-                for (int k = 0; k < 9; ++k) o[11 + k] = st.dth[k] * gsc;
-            }
-        }
+        lam[0] = lam[1] = l;
+        Ps[0] = Ps[1] = P;
+    } else {
+        next_lambda(d0, s0, lam[0], Ps[0]);
     }
-    __syncthreads();
-    // ---- phase B: per-system scalar updates ---------------------------------
-    const int64_t remaining = p.ctr[0];
-    for (int s = threadIdx.x; s < c.n_sys; s += kFinThreads) {
-        const SysDesc &d = p.desc[s];
-        SysState &st = p.state[s];
-        const bool pair_lead = (d.mode == MODE_DCCI_T || d.mode == MODE_DCCI_P) && d.partner > s;
-        const bool pair_follow = (d.mode == MODE_DCCI_T || d.mode == MODE_DCCI_P) && d.partner < s;
-        if (pair_follow) continue;  // handled together with its partner
-        SysState *ss[2] = {&st, pair_lead ? &p.state[d.partner] : nullptr};
-        const SysDesc *dd[2] = {&d, pair_lead ? &p.desc[d.partner] : nullptr};
-        const int m = pair_lead ? 2 : 1;
-        bool start_next = (mode == 2);
-        if (mode == 1) {
-            for (int q = 0; q < m; ++q) {
-                baro_half(*dd[q], *ss[q], c.dt);  // step 9
-                ss[q]->step += 1;
-                ss[q]->k += 1;
-                if (log_every > 0 && log_cap > 0 && (ss[q]->step % log_every) == 0) {
-                    const int sidx = q == 0 ? s : d.partner;
-                    const int64_t row = ((ss[q]->step / log_every) * c.n_sys + sidx) % log_cap;
-                    double *L = p.log + row * 8;
-                    const double nfk = dd[q]->nf * 8.617333262e-5;
-                    L[0] = (double)ss[q]->step;
-                    L[1] = ss[q]->lam;
-                    L[2] = ss[q]->Ps * kGpaPerEvA3;
-                    L[3] = ss[q]->lam != 0.0 ? ss[q]->Ps / ss[q]->lam * kGpaPerEvA3 : 0.0;
-                    L[4] = 2.0 * ss[q]->K / nfk;
-                    L[5] = ss[q]->U_int / (double)dd[q]->n;
-                    L[6] = ss[q]->V / (double)dd[q]->n;
-                    L[7] = ss[q]->W;
-                }
-            }
-            start_next = remaining > 1;
-        }
-        if (!start_next) continue;
-        // ---- start of the next step: switch (1), barostat half (2), factors
-        double lam[2], Ps[2];
-        if (pair_lead) {
-            double l, P;
-            if (!dcci_next(d, st, *dd[1], *ss[1], l, P)) {
-                st.err |= ERR_DCCI;
-                ss[1]->err |= ERR_DCCI;
-            }
-            lam[0] = lam[1] = l;
-            Ps[0] = Ps[1] = P;
-        } else {
-            next_lambda(d, st, lam[0], Ps[0]);
-        }
-        for (int q = 0; q < m; ++q) {
-            apply_switch(*dd[q], *ss[q], lam[q], Ps[q]);
-            baro_half(*dd[q], *ss[q], c.dt);
-            step_factors(*dd[q], *ss[q], c.dt, sw.rc);
-        }
+    for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
+        const int s = q == 0 ? G.s0 : G.s1;
+        apply_switch(p.desc[s], p.state[s], lam[q], Ps[q]);
+        baro_half(p.desc[s], p.state[s], c.dt);
+        step_factors(p.desc[s], p.state[s], c.dt, sw.rc);
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && mode == 1) p.ctr[0] = remaining - 1;
 }
 
-// ----------------------------------------------------------- launchers -----
+// Reductions of one group over its tiles in a fixed order (all threads of
+// the block), then the scalar update by thread 0.
+__device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &sw, const Group &G)
+{
+    __shared__ double red[4][64];
+    __shared__ double sums[2][2 * kNumPart];
+    const int k = threadIdx.x & 63, j = threadIdx.x >> 6, nj = blockDim.x >> 6;
+    for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
+        const SysDesc &d = p.desc[q == 0 ? G.s0 : G.s1];
+        double a = 0.0;
+        if (k < 2 * kNumPart) {
+            const double *src = k < kNumPart ? p.part1 + k : p.part2 + (k - kNumPart);
+            for (int t = d.tile_begin + j; t < d.tile_end; t += nj) a += src[(int64_t)t * kNumPart];
+        }
+        red[j][k] = a;
+        __syncthreads();
+        if (j == 0 && k < 2 * kNumPart) {
+            double s = 0.0;
+            for (int w = 0; w < nj; ++w) s += red[w][k];
+            sums[q][k] = s;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const bool step_end = c.in_step != 0;
+    int64_t remaining = 0;
+    for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
+        const int s = q == 0 ? G.s0 : G.s1;
+        const SysDesc &d = p.desc[s];
+        SysState &st = p.state[s];
+        const double *a = sums[q], *b = sums[q] + kNumPart;
+        st.E2 = a[P_E];
+        st.E3 = a[P_E3];
+        st.U_int = st.E2 + st.E3;
+        for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
+        for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
+        st.U_ref = b[P_UREF];
+        st.K = b[P_K];
+        for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
+        st.V = st.box[0] * st.box[1] * st.box[2];
+        if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
+            st.err |= ERR_NONFINITE;
+        if (p.out) {
+            // dE/dstrain at diagonal strain e: Xi' (I + e)^-T
+            const double gsc = p.grad_scale ? p.grad_scale[s] : 1.0;
+            double *o = p.out + (int64_t)s * 20;
+            o[0] = st.U_int;
+            o[1] = st.U_ref;
+            for (int u = 0; u < 3; ++u)
+                for (int w = 0; w < 3; ++w) o[2 + 3 * u + w] = st.vir[3 * u + w] / st.pscale[w] * gsc;
+            for (int m = 0; m < 9; ++m) o[11 + m] = st.dth[m] * gsc;
+        }
+        if (step_end) {
+            baro_half(d, st, c.dt);  // step 9
+            st.step += 1;
+            st.k += 1;
+            st.remaining -= 1;
+            remaining = st.remaining;
+            if (c.log_every > 0 && c.log_cap > 0 && (st.step % c.log_every) == 0) {
+                const int64_t row = ((st.step / c.log_every) * c.n_sys + s) % c.log_cap;
+                double *L = p.log + row * 8;
+                L[0] = (double)st.step;
+                L[1] = st.lam;
+                L[2] = st.Ps * kGpaPerEvA3;
+                L[3] = st.lam != 0.0 ? st.Ps / st.lam * kGpaPerEvA3 : 0.0;
+                L[4] = 2.0 * st.K / (d.nf * 8.617333262e-5);
+                L[5] = st.U_int / (double)d.n;
+                L[6] = st.V / (double)d.n;
+                L[7] = st.W;
+            }
+        }
+    }
+    if (step_end && remaining > 0) group_start_step(c, p, sw, G);
+}
+
+template <typename R, bool GRAD>
+__global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
+{
+    constexpr int NV = 24;  // -, virial 9, dtheta 9, U_ref, K, noise 3
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
+    const SysDesc &d = p.desc[sys];
+    const SysState &st = p.state[sys];
+    const int64_t N = c.n_total;
+
+    if ((int)threadIdx.x < tile.count) {
+        double box[3], ibox[3];
+        eff_box(st, box, ibox);
+        const int t = tile.start + threadIdx.x;
+        const double4 xa = p.xs[t];
+        const Mom<R> *mom = reinterpret_cast<const Mom<R> *>(p.mom);
+        const Mom<R> mA = mom[t];
+        const R rc = (R)sw.rc, gsig = (R)(sw.gam * sw.sig), c0 = (R)sw.cos0, hle = (R)(0.5 * sw.le);
+        double F3x = 0, F3y = 0, F3z = 0;
+        double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
+        double gg = 0, ga = 0, gs = 0;  // sum H g dln g/d(gamma, a, sigma)
+        const int cnt = p.nl_cnt[t];
+        for (int k = 0; k < cnt; ++k) {
+            const int j = p.nl[(int64_t)k * N + t];
+            const double4 xj = p.xs[j];
+            const double dx = min_image(xj.x - xa.x, box[0], ibox[0]);
+            const double dy = min_image(xj.y - xa.y, box[1], ibox[1]);
+            const double dz = min_image(xj.z - xa.z, box[2], ibox[2]);
+            if (dx * dx + dy * dy + dz * dz >= sw.rc2) continue;
+            const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
+            const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            const R ri = R(1) / r;
+            const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
+            const R den = r - rc;
+            const bool in = den < R(0);
+            const R di = in ? R(1) / den : R(0);
+            const R g = in ? exp(gsig * di) : R(0);
+            const R dg = -g * gsig * di * di;
+            const Mom<R> mJ = mom[j];
+            R tA[3], tJ[3], HA, HJ;
+            d_e3<R>(mA.v, ux, uy, uz, g, dg, ri, c0, hle, tA, HA);
+            d_e3<R>(mJ.v, -ux, -uy, -uz, g, dg, ri, c0, hle, tJ, HJ);
+            F3x += (double)tA[0] - (double)tJ[0];
+            F3y += (double)tA[1] - (double)tJ[1];
+            F3z += (double)tA[2] - (double)tJ[2];
+            vxx += (double)(tA[0] * ddx);
+            vyy += (double)(tA[1] * ddy);
+            vzz += (double)(tA[2] * ddz);
+            vxy += (double)(R(0.5) * (tA[0] * ddy + tA[1] * ddx));
+            vxz += (double)(R(0.5) * (tA[0] * ddz + tA[2] * ddx));
+            vyz += (double)(R(0.5) * (tA[1] * ddz + tA[2] * ddy));
+            if (GRAD) {
+                const R hg = HA * g;
+                gg += (double)(hg * (R)sw.sig * di);
+                ga += (double)(hg * gsig * (R)sw.sig * di * di);
+                gs += (double)(hg * (R)sw.gam * r * di * di);
+            }
+        }
+        acc[1] = vxx;
+        acc[2] = vxy;
+        acc[3] = vxz;
+        acc[4] = vxy;
+        acc[5] = vyy;
+        acc[6] = vyz;
+        acc[7] = vxz;
+        acc[8] = vyz;
+        acc[9] = vzz;
+        if (GRAD) {
+            const double hl = 0.5 * sw.le;
+            acc[14] = hl * ga;  // a
+            acc[16] = hl * gg;  // gamma
+            acc[17] = hl * gs;  // sigma
+        }
+        double4 F = p.fs[t];
+        F.x += F3x;
+        F.y += F3y;
+        F.z += F3z;
+        p.fs[t] = F;
+        // Einstein reference (Frenkel-Ladd systems)
+        double4 x0 = make_double4(0, 0, 0, 0);
+        if (d.mode == MODE_FL) {
+            x0 = p.x0s[t];
+            const double ex = xa.x - x0.x, ey = xa.y - x0.y, ez = xa.z - x0.z;
+            acc[19] = 0.5 * d.k_spring * (ex * ex + ey * ey + ez * ez);
+        }
+        // final half kick of a dynamics step, then the kinetic energy
+        double4 v = p.vs[t];
+        if (c.in_step && d.mode != MODE_FORCE) {
+            const double ka = (0.5 * c.dt) * d.acc;
+            v.x = v.x * st.decay + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring) * st.phi;
+            v.y = v.y * st.decay + ka * total_force(d.mode, st.lam, F.y, xa.y, x0.y, d.k_spring) * st.phi;
+            v.z = v.z * st.decay + ka * total_force(d.mode, st.lam, F.z, xa.z, x0.z, d.k_spring) * st.phi;
+            p.vs[t] = v;
+        }
+        acc[20] = d.mvv2e_m * (v.x * v.x + v.y * v.y + v.z * v.z);
+        // normals of the next O step, for its zero-sum correction
+        if (o_step_on(d)) {
+            double z[3];
+            normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)(p.perm[t] - d.off), z);
+            acc[21] = z[0];
+            acc[22] = z[1];
+            acc[23] = z[2];
+        }
+    }
+    block_reduce<NV>(acc, p.part2 + (int64_t)ti * kNumPart);
+}
+
+// One block per group: fixed-order reductions of the group's tiles and the
+// scalar update (barostat, switch and work, dCCI coupling, next factors).
+__global__ void __launch_bounds__(256) k_finalize(Ctl c, DevPtrs p, SwParams sw)
+{
+    const Group G = p.groups[blockIdx.x];
+    group_finalize(c, p, sw, G);
+}
+
+// Start-of-call prologue: steps left, then the start of the first step.
+__global__ void k_begin_step(Ctl c, DevPtrs p, SwParams sw, int64_t n_steps)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= c.n_groups) return;
+    const Group G = p.groups[g];
+    p.state[G.s0].remaining = n_steps;
+    if (G.s1 >= 0) p.state[G.s1].remaining = n_steps;
+    group_start_step(c, p, sw, G);
+}
+
 // Reset of every system's schedule state (lambda, P_S, work, schedule step)
 // from its descriptor; used at set-up and when a new schedule is installed.
 __global__ void k_reset_schedule(Ctl c, DevPtrs p)
@@ -829,7 +1054,7 @@ __global__ void k_reset_schedule(Ctl c, DevPtrs p)
     st.k = 0;
 }
 
-// Diagonal strain for the next force evaluation (1 = none).
+// Diagonal strain for the next force evaluation (NULL: none).
 __global__ void k_set_pscale(Ctl c, DevPtrs p, const double *diag)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -837,51 +1062,96 @@ __global__ void k_set_pscale(Ctl c, DevPtrs p, const double *diag)
     for (int k = 0; k < 3; ++k) p.state[s].pscale[k] = diag ? 1.0 + diag[3 * s + k] : 1.0;
 }
 
-hipError_t launch_assign_cells(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block,
-                               hipStream_t s)
+__global__ void k_clear_err(Ctl c, DevPtrs p)
 {
-    hipLaunchKernelGGL(k_assign_cells, dim3(c.n_tiles), dim3(block), 0, s, c, p, sw.rc);
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < c.n_sys) p.state[s].err = 0;
+}
+
+// ----------------------------------------------------------- launchers -----
+static inline dim3 tile_grid(const Ctl &c) { return dim3(8 * c.xcd_stride); }
+
+hipError_t launch_iota(const Ctl &c, const DevPtrs &p, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iota, tile_grid(c), dim3(block), 0, s, c, p);
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Ctl &c, const DevPtrs &p, const SwParams &sw, hipStream_t s)
+hipError_t launch_gather(const Ctl &c, const DevPtrs &p, int block, int with_f, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin, dim3(c.n_sys), dim3(kBinThreads), 0, s, c, p, sw.rc);
+    hipLaunchKernelGGL(k_gather, tile_grid(c), dim3(block), 0, s, c, p, with_f);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Ctl &c, const DevPtrs &p, int block, int what, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter, tile_grid(c), dim3(block), 0, s, c, p, what);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block, hipStream_t s)
+{
+    (void)sw;
+    hipLaunchKernelGGL(k_integrate, tile_grid(c), dim3(block), 0, s, c, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block, int stage,
+                          hipStream_t s)
+{
+    switch (stage) {
+        case 0: hipLaunchKernelGGL(k_rb_count, tile_grid(c), dim3(block), 0, s, c, p, sw); break;
+        case 1: hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw); break;
+        case 2: hipLaunchKernelGGL(k_rb_scatter, tile_grid(c), dim3(block), 0, s, c, p); break;
+        case 3: hipLaunchKernelGGL(k_rb_order, tile_grid(c), dim3(block), 0, s, c, p); break;
+        default: {
+            const int S = (block + 7) / 8;
+            const int nv = c.n_tiles * S;
+            hipLaunchKernelGGL(k_rb_list, dim3(8 * ((nv + 7) / 8)), dim3(256), 0, s, c, p, sw, S);
+            break;
+        }
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_pass1(const Ctl &c, const DevPtrs &p, const SwParams &sw, int mixed, int block,
                         hipStream_t s)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_pass1<float>, dim3(c.n_tiles), dim3(block), 0, s, c, p, sw);
-    else
-        hipLaunchKernelGGL(k_pass1<double>, dim3(c.n_tiles), dim3(block), 0, s, c, p, sw);
+    const bool g = (c.flags & 1) != 0;
+    if (mixed) {
+        if (g) hipLaunchKernelGGL((k_pass1<float, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+        else hipLaunchKernelGGL((k_pass1<float, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+    } else {
+        if (g) hipLaunchKernelGGL((k_pass1<double, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+        else hipLaunchKernelGGL((k_pass1<double, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_pass2(const Ctl &c, const DevPtrs &p, const SwParams &sw, int mixed, int block,
                         hipStream_t s)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_pass2<float>, dim3(c.n_tiles), dim3(block), 0, s, c, p, sw);
-    else
-        hipLaunchKernelGGL(k_pass2<double>, dim3(c.n_tiles), dim3(block), 0, s, c, p, sw);
+    const bool g = (c.flags & 1) != 0;
+    if (mixed) {
+        if (g) hipLaunchKernelGGL((k_pass2<float, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+        else hipLaunchKernelGGL((k_pass2<float, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+    } else {
+        if (g) hipLaunchKernelGGL((k_pass2<double, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+        else hipLaunchKernelGGL((k_pass2<double, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Ctl &c, const DevPtrs &p, const SwParams &sw, int mode,
-                           int log_every, int log_cap, hipStream_t s)
+hipError_t launch_finalize(const Ctl &c, const DevPtrs &p, const SwParams &sw, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, c, p, sw, mode, log_every,
-                       log_cap);
+    hipLaunchKernelGGL(k_finalize, dim3(c.n_groups), dim3(256), 0, s, c, p, sw);
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block,
-                            hipStream_t s)
+hipError_t launch_begin_step(const Ctl &c, const DevPtrs &p, const SwParams &sw, int64_t n_steps,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_integrate, dim3(c.n_tiles), dim3(block), 0, s, c, p, sw.rc);
+    hipLaunchKernelGGL(k_begin_step, dim3((c.n_groups + 63) / 64), dim3(64), 0, s, c, p, sw, n_steps);
     return hipGetLastError();
 }
 
@@ -894,6 +1164,12 @@ hipError_t launch_reset_schedule(const Ctl &c, const DevPtrs &p, hipStream_t s)
 hipError_t launch_set_pscale(const Ctl &c, const DevPtrs &p, const double *diag, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_pscale, dim3((c.n_sys + 63) / 64), dim3(64), 0, s, c, p, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_err(const Ctl &c, const DevPtrs &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_err, dim3((c.n_sys + 63) / 64), dim3(64), 0, s, c, p);
     return hipGetLastError();
 }
 }  // namespace swfe

@@ -58,14 +58,16 @@ class SystemState(ctypes.Structure):
                 ("U_int", ctypes.c_double), ("U_ref", ctypes.c_double), ("K", ctypes.c_double),
                 ("V", ctypes.c_double), ("virial", ctypes.c_double * 9), ("box", ctypes.c_double * 3),
                 ("veps", ctypes.c_double), ("T_inst", ctypes.c_double), ("step", ctypes.c_int64),
-                ("sched_k", ctypes.c_int64), ("err", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("sched_k", ctypes.c_int64), ("err", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n_rebuild", ctypes.c_int64)]
 
 
 EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_bytes", "swfe_init_system",
            "swfe_build_neighbors", "swfe_compute_forces", "swfe_set_schedule", "swfe_step_switched",
            "swfe_work_integral", "swfe_get_state", "swfe_set_log", "swfe_read_log", "swfe_set_block",
-           "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats")
-KERNEL_NAMES = ("integrate", "bin", "pass1", "pass2", "finalize")
+           "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats", "swfe_set_skin")
+KERNEL_NAMES = ("integrate", "rebuild_count", "rebuild_scan", "rebuild_scatter", "rebuild_order",
+                "rebuild_list", "pass1", "pass2", "finalize")
 
 _lib = None
 
@@ -101,7 +103,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "swfe_autotune": ([vp, ctypes.POINTER(i32), vp], ctypes.c_int),
         "swfe_sizes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32)], ctypes.c_int),
         "swfe_profile_steps": ([vp, i64, dp, vp], ctypes.c_int),
-        "swfe_neighbor_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32), vp], ctypes.c_int),
+        "swfe_neighbor_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64), vp],
+                                ctypes.c_int),
+        "swfe_set_skin": ([vp, ctypes.c_double, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -264,7 +268,8 @@ class Engine:
         for s in arr:
             out.append(dict(lam=s.lam, Ps=s.Ps, W=s.W, U_int=s.U_int, U_ref=s.U_ref, K=s.K, V=s.V,
                             virial=np.array(s.virial[:]).reshape(3, 3), box=np.array(s.box[:]),
-                            veps=s.veps, T=s.T_inst, step=s.step, sched_k=s.sched_k, err=s.err))
+                            veps=s.veps, T=s.T_inst, step=s.step, sched_k=s.sched_k, err=s.err,
+                            n_rebuild=s.n_rebuild))
         return out
 
     def set_log(self, every: int, capacity: int = 4096):
@@ -291,9 +296,14 @@ class Engine:
         return dict(zip(KERNEL_NAMES, ms))
 
     def neighbor_stats(self):
-        tot, mx = ctypes.c_int64(0), ctypes.c_int32(0)
-        self._check(self.lib.swfe_neighbor_stats(self.ctx, ctypes.byref(tot), ctypes.byref(mx), self._stream()))
-        return int(tot.value), int(mx.value)
+        """(ordered pairs within the cutoff, max per atom, Verlet-list entries)."""
+        tot, mx, ll = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int64(0)
+        self._check(self.lib.swfe_neighbor_stats(self.ctx, ctypes.byref(tot), ctypes.byref(mx),
+                                                 ctypes.byref(ll), self._stream()))
+        return int(tot.value), int(mx.value), int(ll.value)
+
+    def set_skin(self, skin: float):
+        self._check(self.lib.swfe_set_skin(self.ctx, float(skin), self._stream()))
 
     # --------------------------------------------------------------- views --
     def _unpack(self, t, s: int) -> np.ndarray:

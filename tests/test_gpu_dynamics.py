@@ -194,3 +194,23 @@ def test_mixed_precision_dynamics_track_fp64(swfe, sw_params):
     diff = np.abs(res["mixed"] - res["fp64"]) / n
     print(f"mixed-fp64 work difference per atom: {diff}", flush=True)
     assert np.all(diff < 1e-3)
+
+
+@pytest.mark.parametrize("skin", [0.0, 1.0])
+def test_verlet_skin_does_not_change_results(swfe, sw_params, skin):
+    """Lists with any skin (0: rebuilt every step) give the oracle's
+    trajectory; a hot liquid under the barostat rebuilds along the way."""
+    a = liquid_spec(400, 95, mode=inputs.MODE_RS, T0=2500.0, tau_damp=0.1, p_damp=0.2, pressure=1.0,
+                    stream=3, sched_start=1.0, sched_end=0.6, sched_steps=150)
+    eng = swfe.Engine([a], sw_params, dt=0.001, seed=4, precision="fp64")
+    eng.set_skin(skin)
+    o = orc.Oracle([to_oracle(a)], sw_params, dt=0.001, seed=4)
+    eng.step(150)
+    o.run(150)
+    st = eng.state()[0]
+    s = o.systems[0]
+    print(f"skin {skin}: rebuilds {st['n_rebuild']} dx {np.abs(eng.positions(0) - s.x).max():.2e}", flush=True)
+    assert np.abs(eng.positions(0) - s.x).max() < 1e-9
+    assert abs(st["W"] - s.W) < 1e-9 * max(1.0, abs(s.W))
+    assert st["n_rebuild"] >= (150 if skin == 0.0 else 2)
+    eng.close()
