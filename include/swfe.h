@@ -182,6 +182,11 @@ int swfe_build_neighbors(swfe_ctx *ctx, void *stream);
 int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain,
                         const double *grad_scale, double *grad_x, double *out, void *stream);
 
+/* Replace the Stillinger-Weber parameters (theta) of an initialised
+ * context; boxes must stay >= 2 a sigma (SWFE_E_BOX_TOO_SMALL otherwise).
+ * The interaction is not re-evaluated: call swfe_compute_forces. */
+int swfe_set_params(swfe_ctx *ctx, const swfe_sw_params *p);
+
 /* Install new schedules (sched_start/sched_end/sched_steps of the given
  * descriptors; NULL keeps the current ones) and reset the schedule step and
  * work accumulators of every system.  Does not synchronise. */

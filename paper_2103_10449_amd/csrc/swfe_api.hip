@@ -579,6 +579,18 @@ int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain, con
     return SWFE_OK;
 }
 
+int swfe_set_params(swfe_ctx *ctx, const swfe_sw_params *p)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!p) return fail(ctx, SWFE_E_INVALID_ARG, "null parameters");
+    Plan P;
+    RCHK(plan_systems(ctx, ctx->hdesc.data(), ctx->n_sys, p, ctx->dt, ctx->skin, P));
+    ctx->hsw = *p;
+    ctx->sw = make_sw(*p);
+    drop_graph(ctx);
+    return SWFE_OK;
+}
+
 int swfe_set_schedule(swfe_ctx *ctx, const swfe_system_desc *d, void *stream)
 {
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");

@@ -65,7 +65,8 @@ class SystemState(ctypes.Structure):
 EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_bytes", "swfe_init_system",
            "swfe_build_neighbors", "swfe_compute_forces", "swfe_set_schedule", "swfe_step_switched",
            "swfe_work_integral", "swfe_get_state", "swfe_set_log", "swfe_read_log", "swfe_set_block",
-           "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats", "swfe_set_skin")
+           "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats", "swfe_set_skin",
+           "swfe_set_params")
 KERNEL_NAMES = ("integrate", "rebuild_count", "rebuild_scan", "rebuild_scatter", "rebuild_order",
                 "rebuild_list", "pass1", "pass2", "finalize")
 
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "swfe_neighbor_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64), vp],
                                 ctypes.c_int),
         "swfe_set_skin": ([vp, ctypes.c_double, vp], ctypes.c_int),
+        "swfe_set_params": ([vp, ctypes.POINTER(SwParams)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -245,6 +247,12 @@ class Engine:
             ctypes.c_void_p(grad_x.data_ptr()) if grad_x is not None else None,
             ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out
+
+    def set_params(self, params: dict):
+        """New Stillinger-Weber parameters (dict with the keys of PARAM_NAMES, cos0, mass)."""
+        self.params = dict(params)
+        self._sw = sw_params_struct(self.params)
+        self._check(self.lib.swfe_set_params(self.ctx, ctypes.byref(self._sw)))
 
     def set_schedule(self, specs: Optional[Sequence] = None):
         desc = system_descs(specs) if specs is not None else None
