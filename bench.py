@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the batched replicas of this workload do not "
@@ -154,6 +156,15 @@ def main():
     import torch
     from paper_2103_10449_amd import inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 5}))
+        return
     P = dict(inputs.SW_SILICON)
     seed = inputs.SEED0
     steps = max(2, args.steps - args.steps % 2)

@@ -30,8 +30,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s;
-    size_t perm, tperm, norder, rank, cellid, nnb, cell_count, cell_start, nl, nl_cnt, mom, e_s;
-    size_t part1, part2, disp_max, desc, state, tiles, groups, log, strain, total;
+    size_t perm, tperm, norder, rank, cellid, nnb, sl, cell_count, cell_start, nl, nl_cnt, mom, e_s;
+    size_t part1, part2, disp_max, work, n_work, desc, state, tiles, groups, log, strain, total;
 };
 
 struct Plan {
@@ -252,11 +252,14 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.cell_start = take(4 * ((size_t)cells + n_sys));
     L.nl = take(4 * n * kMaxList);
     L.nl_cnt = take(4 * n);
+    L.sl = take(4 * n * kMaxShort);
     L.mom = take(8 * 12 * n);
     L.e_s = take(8 * n);
     L.part1 = take(8 * (size_t)tiles * kNumPart);
     L.part2 = take(8 * (size_t)tiles * kNumPart);
     L.disp_max = take(8 * 2 * (size_t)n_sys);
+    L.work = take(4 * (size_t)tiles);
+    L.n_work = take(16);
     L.desc = take(sizeof(SysDesc) * n_sys);
     L.state = take(sizeof(SysState) * n_sys);
     L.tiles = take(sizeof(Tile) * (size_t)tiles);
@@ -497,11 +500,14 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     q.cell_start = (int32_t *)(w + L.cell_start);
     q.nl = (int32_t *)(w + L.nl);
     q.nl_cnt = (int32_t *)(w + L.nl_cnt);
+    q.sl = (int32_t *)(w + L.sl);
     q.mom = (void *)(w + L.mom);
     q.e_s = (double *)(w + L.e_s);
     q.part1 = (double *)(w + L.part1);
     q.part2 = (double *)(w + L.part2);
     q.disp_max = (double *)(w + L.disp_max);
+    q.work = (int32_t *)(w + L.work);
+    q.n_work = (int32_t *)(w + L.n_work);
     q.desc = (const SysDesc *)(w + L.desc);
     q.state = (SysState *)(w + L.state);
     q.tiles = (const Tile *)(w + L.tiles);

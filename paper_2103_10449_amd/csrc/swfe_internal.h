@@ -8,9 +8,11 @@
 namespace swfe {
 
 constexpr int kMaxList = 64;       // Verlet-list capacity per atom (within rc + skin)
+constexpr int kMaxShort = 48;      // neighbours within rc per atom (pass 1 -> pass 2)
 constexpr int kSortThreads = 1024; // threads of the per-system sort workgroup
 constexpr int kNumKernels = 9;     // launches of one dynamics step (for profiling)
-constexpr int kRebuildStages = 5;  // launches of a list rebuild
+constexpr int kRebuildStages = 5;  // rebuild stages (the first is two launches)
+constexpr int kWorkGrid = 512;     // blocks of the work-list rebuild kernels
 
 // Per-tile partial sums of the two force passes (fixed slots).
 enum : int {
@@ -113,9 +115,11 @@ struct DevPtrs {
     int32_t *cell_count, *cell_start;
     int32_t *nl, *nl_cnt;                 // Verlet list [kMaxList][n_total] of sorted positions
     int32_t *nnb;                         // neighbours within rc per atom (last pass 1)
+    int32_t *sl;                          // [kMaxShort][n_total] those neighbours (sorted positions)
     void *mom;                            // [n_total][12] moments in term precision
     double *e_s;                          // per-atom energy, sorted order
     double *part1, *part2;                // [n_tiles][kNumPart]
+    int32_t *work, *n_work;               // tiles to rebuild in this step, and their count
     double *disp_max;                     // [n_sys][2] max squared displacement since build
                                           // (two slots alternate between steps)
     const SysDesc *desc;

@@ -6,11 +6,12 @@
 // caller's atom index at sorted position t.  Neighbour lists hold sorted
 // positions, so neighbours of a tile are nearby in memory.
 //
-// One dynamics step is nine launches over all systems at once:
+// One dynamics step is ten launches over all systems at once:
 //   integrate    B kick, A drift, O Langevin, A drift; per-tile maximum
 //                displacement since the last list build
 //   rebuild 0-4  (only systems whose list may miss a pair do any work)
-//                0 count:   cell index and rank within the cell
+//                0 decide:  one block lists the tiles of stale systems;
+//                  count:   cell index and rank within the cell
 //                1 scan:    per-system cell starts
 //                2 scatter: atom data into its cell's segment (staging)
 //                3 order:   in-cell order by the caller's atom index
@@ -345,33 +346,63 @@ __device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, i
     return 2.0 * sqrt(m) + (sw.rc + d.skin) * shrink > d.skin;
 }
 
+// One block: the rebuild decision of every system and the compact list of
+// the tiles to rebuild (p.work[0..n_work)), so that the rebuild stages cost
+// almost nothing on steps where no list is stale.
+__global__ void __launch_bounds__(256) k_rb_decide(Ctl c, DevPtrs p, SwParams sw)
+{
+    __shared__ int scan[256];
+    int base = 0;
+    for (int s0 = 0; s0 < c.n_sys; s0 += 256) {
+        const int sys = s0 + (int)threadIdx.x;
+        int nt = 0;
+        bool rb = false;
+        if (sys < c.n_sys) {
+            rb = list_stale(c, p, sw, sys);
+            SysState &st = p.state[sys];
+            st.rb = rb ? 1 : 0;
+            // clear the slot the next step's integrate fills (both on a forced build)
+            p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
+            if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
+            if (rb) nt = p.desc[sys].tile_end - p.desc[sys].tile_begin;
+        }
+        scan[threadIdx.x] = nt;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int add = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (rb) {
+            const int at = base + scan[threadIdx.x] - nt;
+            const int tb = p.desc[sys].tile_begin;
+            for (int q = 0; q < nt; ++q) p.work[at + q] = tb + q;
+        }
+        base += scan[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.n_work[0] = base;
+}
+
 __global__ void __launch_bounds__(256) k_rb_count(Ctl c, DevPtrs p, SwParams sw)
 {
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
-    const Tile tile = p.tiles[ti];
-    const int sys = tile.sys;
-    const bool rb = list_stale(c, p, sw, sys);
-    if (threadIdx.x == 0) {
-        p.state[sys].rb = rb ? 1 : 0;
-        // clear the slot the next step's integrate fills (both on a forced build)
-        if (ti == p.desc[sys].tile_begin) {
-            const int64_t step = p.state[sys].step;
-            p.disp_max[2 * sys + ((step + 1) & 1)] = 0.0;
-            if (c.force_rebuild) p.disp_max[2 * sys + (step & 1)] = 0.0;
-        }
+    const int n_work = p.n_work[0];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const Tile tile = p.tiles[p.work[w]];
+        if ((int)threadIdx.x >= tile.count) continue;
+        const int sys = tile.sys;
+        const SysDesc &d = p.desc[sys];
+        const SysState &st = p.state[sys];
+        double box[3], ibox[3];
+        int nc[3];
+        eff_box(st, box, ibox);
+        cell_grid(d, box, sw.rc + d.skin, nc);
+        const int t = tile.start + threadIdx.x;
+        const int cell = cell_of_pos(p.xs[t], ibox, nc);
+        p.cellid[t] = cell;
+        p.rank[t] = atomicAdd(&p.cell_count[d.cell_base + cell], 1);
     }
-    if (!rb || (int)threadIdx.x >= tile.count) return;
-    const SysDesc &d = p.desc[sys];
-    const SysState &st = p.state[sys];
-    double box[3], ibox[3];
-    int nc[3];
-    eff_box(st, box, ibox);
-    cell_grid(d, box, sw.rc + d.skin, nc);
-    const int t = tile.start + threadIdx.x;
-    const int cell = cell_of_pos(p.xs[t], ibox, nc);
-    p.cellid[t] = cell;
-    p.rank[t] = atomicAdd(&p.cell_count[d.cell_base + cell], 1);
 }
 
 // One workgroup per system: exclusive scan of the cell counts into cell
@@ -421,48 +452,50 @@ __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwPa
 // the order inside a cell is not yet fixed).
 __global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p)
 {
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
-    const Tile tile = p.tiles[ti];
-    const int sys = tile.sys;
-    if (!p.state[sys].rb || (int)threadIdx.x >= tile.count) return;
-    const SysDesc &d = p.desc[sys];
-    const int t = tile.start + threadIdx.x;
-    const int cell = p.cellid[t];
-    const int s = p.cell_start[d.cell_base + sys + cell] + p.rank[t];
-    p.txs[s] = p.xs[t];
-    p.tvs[s] = p.vs[t];
-    p.tfs[s] = p.fs[t];
-    if (p.x0) p.tx0s[s] = p.x0s[t];
-    p.tperm[s] = p.perm[t];
-    p.norder[s] = cell;
+    const int n_work = p.n_work[0];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const Tile tile = p.tiles[p.work[w]];
+        if ((int)threadIdx.x >= tile.count) continue;
+        const int sys = tile.sys;
+        const SysDesc &d = p.desc[sys];
+        const int t = tile.start + threadIdx.x;
+        const int cell = p.cellid[t];
+        const int s = p.cell_start[d.cell_base + sys + cell] + p.rank[t];
+        p.txs[s] = p.xs[t];
+        p.tvs[s] = p.vs[t];
+        p.tfs[s] = p.fs[t];
+        if (p.x0) p.tx0s[s] = p.x0s[t];
+        p.tperm[s] = p.perm[t];
+        p.norder[s] = cell;
+    }
 }
 
 // Final order: inside a cell atoms follow the caller's atom index.  Each
 // staged atom counts the smaller indices of its cell and moves there.
 __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
 {
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
-    const Tile tile = p.tiles[ti];
-    const int sys = tile.sys;
-    if (!p.state[sys].rb || (int)threadIdx.x >= tile.count) return;
-    const SysDesc &d = p.desc[sys];
-    const int i = tile.start + threadIdx.x;
-    const int cell = p.norder[i];
-    const int32_t *start = p.cell_start + d.cell_base + sys;
-    const int b = start[cell], e = start[cell + 1];
-    const int key = p.tperm[i];
-    int rank = 0;
-    for (int j = b; j < e; ++j) rank += p.tperm[j] < key ? 1 : 0;
-    const int s = b + rank;
-    const double4 x = p.txs[i];
-    p.xs[s] = x;
-    p.xb[s] = x;
-    p.vs[s] = p.tvs[i];
-    p.fs[s] = p.tfs[i];
-    if (p.x0) p.x0s[s] = p.tx0s[i];
-    p.perm[s] = key;
+    const int n_work = p.n_work[0];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const Tile tile = p.tiles[p.work[w]];
+        if ((int)threadIdx.x >= tile.count) continue;
+        const int sys = tile.sys;
+        const SysDesc &d = p.desc[sys];
+        const int i = tile.start + threadIdx.x;
+        const int cell = p.norder[i];
+        const int32_t *start = p.cell_start + d.cell_base + sys;
+        const int b = start[cell], e = start[cell + 1];
+        const int key = p.tperm[i];
+        int rank = 0;
+        for (int j = b; j < e; ++j) rank += p.tperm[j] < key ? 1 : 0;
+        const int s = b + rank;
+        const double4 x = p.txs[i];
+        p.xs[s] = x;
+        p.xb[s] = x;
+        p.vs[s] = p.tvs[i];
+        p.fs[s] = p.tfs[i];
+        if (p.x0) p.x0s[s] = p.tx0s[i];
+        p.perm[s] = key;
+    }
 }
 
 // Verlet list of sorted positions within rc + skin from the (up to) 27 cells
@@ -472,15 +505,10 @@ __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
 // gives every cell its slot range, so the list is in stencil-cell order and,
 // inside a cell, in sorted order.  Blocks of 256 threads hold 8 atoms; S
 // blocks cover one tile.
-__global__ void __launch_bounds__(256) k_rb_list(Ctl c, DevPtrs p, SwParams sw, int S)
+__device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const SwParams &sw, int ti, int sub)
 {
-    const int nv = c.n_tiles * S;
-    const int v = (blockIdx.x & 7) * ((nv + 7) / 8) + (blockIdx.x >> 3);
-    if (v >= nv) return;
-    const int ti = v / S, sub = v % S;
     const Tile tile = p.tiles[ti];
     const int sys = tile.sys;
-    if (!p.state[sys].rb) return;
     const int a_loc = sub * 8 + (threadIdx.x >> 5);
     const int lane = threadIdx.x & 31;
     const bool valid = a_loc < tile.count;
@@ -538,10 +566,18 @@ __global__ void __launch_bounds__(256) k_rb_list(Ctl c, DevPtrs p, SwParams sw, 
         if (slot < kMaxList) p.nl[(int64_t)slot * N + s] = b + k;
         ++slot;
     }
-    if (!valid) return;
-    if (over || total > kMaxList) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
-    if (lane == 0) p.nl_cnt[s] = total < kMaxList ? total : kMaxList;
+    if (valid) {
+        if (over || total > kMaxList) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
+        if (lane == 0) p.nl_cnt[s] = total < kMaxList ? total : kMaxList;
+    }
 }
+
+__global__ void __launch_bounds__(256) k_rb_list(Ctl c, DevPtrs p, SwParams sw, int S)
+{
+    const int nv = p.n_work[0] * S;
+    for (int v = blockIdx.x; v < nv; v += gridDim.x) list_block(c, p, sw, p.work[v / S], v % S);
+}
+
 
 // ---------------------------------------------------------------- pass 1 ---
 // Pair terms (energy, force, virial, parameter derivative: half per ordered
@@ -578,13 +614,22 @@ __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
         double F2x = 0, F2y = 0, F2z = 0;
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
         int nin = 0;
+        // software pipeline: the next candidate's index and position are in
+        // flight while this one is evaluated
+        int jn = cnt > 0 ? p.nl[t] : t;
+        int jnn = cnt > 1 ? p.nl[N + t] : t;
+        double4 xn = p.xs[jn];
         for (int k = 0; k < cnt; ++k) {
-            const int j = p.nl[(int64_t)k * N + t];
-            const double4 xj = p.xs[j];
+            const int j = jn;
+            const double4 xj = xn;
+            jn = jnn;
+            xn = p.xs[jn];
+            jnn = k + 2 < cnt ? p.nl[(int64_t)(k + 2) * N + t] : t;
             const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
             const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
             const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
             if (dx * dx + dy * dy + dz * dz >= sw.rc2) continue;
+            if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = j;
             ++nin;
             const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
             const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
@@ -663,7 +708,8 @@ __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
         for (int k = 0; k < 11; ++k) mo.v[k] = (R)m[k];
         mo.v[11] = R(0);
         reinterpret_cast<Mom<R> *>(p.mom)[t] = mo;
-        p.nnb[t] = nin;
+        if (nin > kMaxShort) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
+        p.nnb[t] = nin < kMaxShort ? nin : kMaxShort;
         p.fs[t] = make_double4(F2x, F2y, F2z, 0.0);
         p.e_s[t] = acc[0] + acc[19];
     }
@@ -929,14 +975,21 @@ __global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
         double F3x = 0, F3y = 0, F3z = 0;
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
         double gg = 0, ga = 0, gs = 0;  // sum H g dln g/d(gamma, a, sigma)
-        const int cnt = p.nl_cnt[t];
+        // the neighbours within rc that pass 1 found at these positions
+        const int cnt = p.nnb[t];
+        int jn = cnt > 0 ? p.sl[t] : t;
+        int jnn = cnt > 1 ? p.sl[N + t] : t;
+        double4 xn = p.xs[jn];
         for (int k = 0; k < cnt; ++k) {
-            const int j = p.nl[(int64_t)k * N + t];
-            const double4 xj = p.xs[j];
+            const int j = jn;
+            const double4 xj = xn;
+            jn = jnn;
+            xn = p.xs[jn];
+            jnn = k + 2 < cnt ? p.sl[(int64_t)(k + 2) * N + t] : t;
+            const Mom<R> mJ = mom[j];
             const double dx = min_image(xj.x - xa.x, box[0], ibox[0]);
             const double dy = min_image(xj.y - xa.y, box[1], ibox[1]);
             const double dz = min_image(xj.z - xa.z, box[2], ibox[2]);
-            if (dx * dx + dy * dy + dz * dz >= sw.rc2) continue;
             const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
             const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             const R ri = R(1) / r;
@@ -946,7 +999,6 @@ __global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
             const R di = in ? R(1) / den : R(0);
             const R g = in ? exp(gsig * di) : R(0);
             const R dg = -g * gsig * di * di;
-            const Mom<R> mJ = mom[j];
             R tA[3], tJ[3], HA, HJ;
             d_e3<R>(mA.v, ux, uy, uz, g, dg, ri, c0, hle, tA, HA);
             d_e3<R>(mJ.v, -ux, -uy, -uz, g, dg, ri, c0, hle, tJ, HJ);
@@ -1100,16 +1152,16 @@ hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, in
                           hipStream_t s)
 {
     switch (stage) {
-        case 0: hipLaunchKernelGGL(k_rb_count, tile_grid(c), dim3(block), 0, s, c, p, sw); break;
-        case 1: hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw); break;
-        case 2: hipLaunchKernelGGL(k_rb_scatter, tile_grid(c), dim3(block), 0, s, c, p); break;
-        case 3: hipLaunchKernelGGL(k_rb_order, tile_grid(c), dim3(block), 0, s, c, p); break;
-        default: {
-            const int S = (block + 7) / 8;
-            const int nv = c.n_tiles * S;
-            hipLaunchKernelGGL(k_rb_list, dim3(8 * ((nv + 7) / 8)), dim3(256), 0, s, c, p, sw, S);
+        case 0:
+            hipLaunchKernelGGL(k_rb_decide, dim3(1), dim3(256), 0, s, c, p, sw);
+            hipLaunchKernelGGL(k_rb_count, dim3(kWorkGrid), dim3(block), 0, s, c, p, sw);
             break;
-        }
+        case 1: hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw); break;
+        case 2: hipLaunchKernelGGL(k_rb_scatter, dim3(kWorkGrid), dim3(block), 0, s, c, p); break;
+        case 3: hipLaunchKernelGGL(k_rb_order, dim3(kWorkGrid), dim3(block), 0, s, c, p); break;
+        default:
+            hipLaunchKernelGGL(k_rb_list, dim3(4 * kWorkGrid), dim3(256), 0, s, c, p, sw, (block + 7) / 8);
+            break;
     }
     return hipGetLastError();
 }
