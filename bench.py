@@ -45,7 +45,7 @@ def kernel_flops(name, n_atoms, ordered_pairs):
     return None
 
 
-def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps):
+def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, skins=None):
     import torch
     from paper_2103_10449_amd import swfe
 
@@ -63,7 +63,7 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps):
         s.sched_start, s.sched_end, s.sched_steps = a, a, 0
     eng.set_schedule(specs)
     best = None
-    for skin in SKINS:
+    for skin in (skins or SKINS):
         eng.set_skin(skin)
         eng.step(5, use_graph=True)
         torch.cuda.synchronize()
@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="fixed Verlet skin in A (default: chosen by timing during warm-up)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
@@ -172,12 +174,13 @@ def main():
     print(f"# workload: {base.n_atoms} atoms in {len(base.systems)} replicas", file=sys.stderr, flush=True)
     builder = lambda half: base
 
-    mixed = run_precision("mixed", builder, steps, args.warmup, P, seed, args.profile_steps)
+    skins = (args.skin,) if args.skin > 0 else None
+    mixed = run_precision("mixed", builder, steps, args.warmup, P, seed, args.profile_steps, skins)
     print(f"# mixed: {mixed['n_atoms']} atoms, {mixed['steps']} steps in {mixed['wall']:.3f} s "
           f"(block {mixed['block']}, {mixed['pairs'] / mixed['n_atoms']:.2f} neighbours/atom)", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_precision("fp64", builder, steps, args.warmup, P, seed, args.profile_steps)
+        fp64 = run_precision("fp64", builder, steps, args.warmup, P, seed, args.profile_steps, skins)
         print(f"# fp64: {fp64['steps']} steps in {fp64['wall']:.3f} s", file=sys.stderr, flush=True)
 
     value = mixed["n_atoms"] * mixed["steps"] / mixed["wall"]
@@ -200,7 +203,8 @@ def main():
                    "replicas": mixed["n_rep"], "atoms": mixed["n_atoms"], "precision": "mixed",
                    "dt_ps": 0.001, "forward_steps": steps // 2, "backward_steps": steps // 2,
                    "block": mixed["block"], "skin_A": mixed["skin"],
-                   "list_rebuilds_per_step": mixed["n_rebuild"] / (mixed["steps"] + args.warmup + 45 * len(SKINS))},
+                   "list_rebuilds_per_step": mixed["n_rebuild"] / (mixed["steps"] + args.warmup +
+                                                                   45 * len(skins or SKINS))},
     }
     if fp64 is not None:
         v64 = fp64["n_atoms"] * fp64["steps"] / fp64["wall"]

@@ -29,7 +29,7 @@ constexpr double kDefaultSkin = 0.5;                                    // A
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s;
+    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s, zs;
     size_t perm, tperm, norder, rank, cellid, nnb, sl, cell_count, cell_start, nl, nl_cnt, mom, e_s;
     size_t part1, part2, disp_max, work, n_work, desc, state, tiles, groups, log, strain, total;
 };
@@ -242,6 +242,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.tvs = take(d4 * n);
     L.tfs = take(d4 * n);
     L.tx0s = take(d4 * n);
+    L.zs = take(d4 * n);
     L.perm = take(4 * n);
     L.tperm = take(4 * n);
     L.norder = take(4 * n);
@@ -490,6 +491,7 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     q.tvs = (double4 *)(w + L.tvs);
     q.tfs = (double4 *)(w + L.tfs);
     q.tx0s = (double4 *)(w + L.tx0s);
+    q.zs = (double4 *)(w + L.zs);
     q.perm = (int32_t *)(w + L.perm);
     q.tperm = (int32_t *)(w + L.tperm);
     q.norder = (int32_t *)(w + L.norder);
@@ -547,6 +549,8 @@ int swfe_build_neighbors(swfe_ctx *ctx, void *stream)
     Ctl k = make_ctl(ctx, 0, 0, 1);
     HIPCHK(ctx, launch_gather(k, ctx->ptrs, ctx->block, 1, s));
     RCHK(enqueue_rebuild(ctx, ctx->ptrs, k, s));
+    // the stored normals of the next O step follow the new atom order
+    HIPCHK(ctx, launch_fill_noise(k, ctx->ptrs, ctx->block, s));
     HIPCHK(ctx, launch_scatter(k, ctx->ptrs, ctx->block, 1 | 2, s));
     return SWFE_OK;
 }

@@ -111,6 +111,7 @@ struct DevPtrs {
     // internal arrays, cell-sorted order
     double4 *xs, *vs, *fs, *x0s, *xb;     // positions, velocities, F_int, anchors, build positions
     double4 *txs, *tvs, *tfs, *tx0s;      // permutation staging
+    double4 *zs;                          // normals of the next O step, sorted order
     int32_t *perm, *tperm, *norder, *rank, *cellid;  // norder: staged cell index
     int32_t *cell_count, *cell_start;
     int32_t *nl, *nl_cnt;                 // Verlet list [kMaxList][n_total] of sorted positions
@@ -141,6 +142,7 @@ hipError_t launch_integrate(const Ctl &c, const DevPtrs &p, const SwParams &sw, 
                             hipStream_t s);
 hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block, int stage,
                           hipStream_t s);
+hipError_t launch_fill_noise(const Ctl &c, const DevPtrs &p, int block, hipStream_t s);
 hipError_t launch_pass1(const Ctl &c, const DevPtrs &p, const SwParams &sw, int mixed, int block,
                         hipStream_t s);
 hipError_t launch_pass2(const Ctl &c, const DevPtrs &p, const SwParams &sw, int mixed, int block,

@@ -16,9 +16,12 @@
 //                2 scatter: atom data into its cell's segment (staging)
 //                3 order:   in-cell order by the caller's atom index
 //                4 list:    Verlet list within rc + skin from the 27 cells
-//   pass1        pair terms and the 11 three-body moments per atom
+//   pass1        filter of the Verlet list to the short list (within rc),
+//                then pair terms and the 11 three-body moments per atom
 //   pass2        three-body force gather from own and neighbour moments,
-//                Einstein springs, final B kick, per-tile partial sums
+//                Einstein springs, final B kick, per-tile partial sums, the
+//                normals of the next O step (stored, and summed for its
+//                zero-sum correction)
 //   finalize     one block per group (a system or a dCCI pair): fixed-order
 //                reduction of its tiles, the barostat, the lambda switch and
 //                work increment, the dCCI coupling and the integrator
@@ -143,12 +146,16 @@ __device__ __forceinline__ void normals3(uint64_t seed, uint64_t stream, uint64_
     double u1 = ((double)(c1 >> 11) + 1.0) * two53;
     double u2 = ((double)(c2 >> 11) + 1.0) * two53;
     double u3 = ((double)(c3 >> 11) + 1.0) * two53;
-    const double twopi = 2.0 * 3.141592653589793;
-    double r01 = sqrt(-2.0 * log(u0));
-    double r23 = sqrt(-2.0 * log(u2));
-    out[0] = r01 * cos(twopi * u1);
-    out[1] = r01 * sin(twopi * u1);
-    out[2] = r23 * cos(twopi * u3);
+    // cos(2 pi u) and sin(2 pi u) through sincospi(2 u): 2 u is exact and
+    // lies in (0, 2], so no general argument reduction is needed
+    const double r01 = sqrt(-2.0 * log(u0));
+    const double r23 = sqrt(-2.0 * log(u2));
+    double sn1, cs1, sn3, cs3;
+    sincospi(2.0 * u1, &sn1, &cs1);
+    sincospi(2.0 * u3, &sn3, &cs3);
+    out[0] = r01 * cs1;
+    out[1] = r01 * sn1;
+    out[2] = r23 * cs3;
 }
 
 __device__ __forceinline__ bool o_step_on(const SysDesc &d)
@@ -270,6 +277,22 @@ __global__ void __launch_bounds__(256) k_scatter(Ctl c, DevPtrs p, int what)
     }
 }
 
+// Normals of the next O step for every atom in the current order (after a
+// list build outside a step reorders the atoms).
+__global__ void __launch_bounds__(256) k_fill_noise(Ctl c, DevPtrs p)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    if ((int)threadIdx.x >= tile.count) return;
+    const SysDesc &d = p.desc[tile.sys];
+    if (!o_step_on(d)) return;
+    const int t = tile.start + threadIdx.x;
+    double z[3];
+    normals3(c.seed, d.stream, (uint64_t)p.state[tile.sys].step, (uint64_t)(p.perm[t] - d.off), z);
+    p.zs[t] = make_double4(z[0], z[1], z[2], 0.0);
+}
+
 // ------------------------------------------------------------- integrate ---
 // Steps 3-6 of the switched step for one atom: B kick with F(lambda_{k+1}),
 // A half drift with isotropic box scaling, O Langevin step with zero-sum
@@ -299,12 +322,13 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p)
             x.y = x.y * st.grow + (v.y * hdt) * st.psi;
             x.z = x.z * st.grow + (v.z * hdt) * st.psi;
             if (o_step_on(d)) {
-                double z[3];
-                normals3(c.seed, d.stream, (uint64_t)st.step, (uint64_t)(p.perm[t] - d.off), z);
+                // this step's normals, drawn by the force pass that ended
+                // the previous step (it also formed their mean)
+                const double4 z = p.zs[t];
                 const double c2s = d.c2 * d.sigv;
-                v.x = d.c1 * v.x + c2s * (z[0] - st.noise_mean[0]);
-                v.y = d.c1 * v.y + c2s * (z[1] - st.noise_mean[1]);
-                v.z = d.c1 * v.z + c2s * (z[2] - st.noise_mean[2]);
+                v.x = d.c1 * v.x + c2s * (z.x - st.noise_mean[0]);
+                v.y = d.c1 * v.y + c2s * (z.y - st.noise_mean[1]);
+                v.z = d.c1 * v.z + c2s * (z.z - st.noise_mean[2]);
             }
             x.x = x.x * st.grow + (v.x * hdt) * st.psi;
             x.y = x.y * st.grow + (v.y * hdt) * st.psi;
@@ -588,8 +612,53 @@ struct alignas(16) Mom {
     R v[12];
 };
 
+// Term arithmetic.  FP32 terms use the hardware reciprocal, reciprocal
+// square root, exponential and logarithm (about 1 ulp each, no IEEE
+// correction steps); FP64 terms use the correctly rounded operations.
+template <typename R>
+struct Fm;
+
+template <>
+struct Fm<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    // distance and its inverse from the squared distance
+    static __device__ __forceinline__ void dist(float r2, float &r, float &ri)
+    {
+        ri = __builtin_amdgcn_rsqf(r2);
+        r = r2 * ri;
+    }
+    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    static __device__ __forceinline__ float log(float x) { return __logf(x); }
+};
+
+template <>
+struct Fm<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ void dist(double r2, double &r, double &ri)
+    {
+        r = ::sqrt(r2);
+        ri = 1.0 / r;
+    }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double log(double x) { return ::log(x); }
+};
+
+// Gather batch sizes: list candidates (filter), short-list neighbours in
+// pass 1 and in pass 2.
+constexpr int kBatchA = 8, kBatchB = 4, kBatch2 = 4;
+
+// Entry k of atom t's list ([row][n_total] layout, n valid rows, n >= 1).
+// Rows past the end read the last valid row (no branch around the load) and
+// yield t itself, whose position is always valid to load.
+__device__ __forceinline__ int list_entry(const int32_t *list, int k, int n, int64_t N, int t)
+{
+    const int row = k < n ? k : n - 1;
+    const int j = list[(int64_t)row * N + t];
+    return k < n ? j : t;
+}
+
 template <typename R, bool GRAD>
-__global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 {
     constexpr int NV = 20;  // E2, virial 9, dtheta 9, E3
     double acc[NV];
@@ -608,80 +677,104 @@ __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
         const int t = tile.start + threadIdx.x;
         const double4 xi = p.xs[t];
         const int cnt = p.nl_cnt[t];
+        // Filter: the list candidates now within rc go to the short list.
+        // It is cheap per candidate, so lanes whose candidates are mostly
+        // outside rc do not hold the wave in the term evaluation below.
+        int nin = 0;
+        // batches of kBatchA candidates: all their indices, then all their
+        // positions, are in flight together
+        for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
+            int jb[kBatchA];
+#pragma unroll
+            for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
+            double4 xj[kBatchA];
+#pragma unroll
+            for (int u = 0; u < kBatchA; ++u) xj[u] = p.xs[jb[u]];
+#pragma unroll
+            for (int u = 0; u < kBatchA; ++u) {
+                const double dx = min_image(xj[u].x - xi.x, box[0], ibox[0]);
+                const double dy = min_image(xj[u].y - xi.y, box[1], ibox[1]);
+                const double dz = min_image(xj[u].z - xi.z, box[2], ibox[2]);
+                if (k0 + u < cnt && dx * dx + dy * dy + dz * dz < sw.rc2) {
+                    if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = jb[u];
+                    ++nin;
+                }
+            }
+        }
+        const int ns = nin < kMaxShort ? nin : kMaxShort;
         const R rc = (R)sw.rc, sig = (R)sw.sig, eA = (R)sw.eA, B = (R)sw.B, pp = (R)sw.p,
                 qq = (R)sw.q, gsig = (R)(sw.gam * sw.sig);
         double m[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         double F2x = 0, F2y = 0, F2z = 0;
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
-        int nin = 0;
-        // software pipeline: the next candidate's index and position are in
-        // flight while this one is evaluated
-        int jn = cnt > 0 ? p.nl[t] : t;
-        int jnn = cnt > 1 ? p.nl[N + t] : t;
-        double4 xn = p.xs[jn];
-        for (int k = 0; k < cnt; ++k) {
-            const int j = jn;
-            const double4 xj = xn;
-            jn = jnn;
-            xn = p.xs[jn];
-            jnn = k + 2 < cnt ? p.nl[(int64_t)(k + 2) * N + t] : t;
-            const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
-            const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
-            const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
-            if (dx * dx + dy * dy + dz * dz >= sw.rc2) continue;
-            if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = j;
-            ++nin;
-            const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
-            const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            const R ri = R(1) / r;
-            const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
-            // inside the cutoff in FP64 may round to r >= rc in the term
-            // precision; the terms vanish there, so they are zeroed
-            const R den = r - rc;
-            const bool in = den < R(0);
-            const R di = in ? R(1) / den : R(0);
-            const R sr = sig * ri;
-            const R sp = powi_or_pow(sr, sw.ip, pp);
-            const R sq = powi_or_pow(sr, sw.iq, qq);
-            const R ex = in ? exp(sig * di) : R(0);
-            const R br = B * sp - sq;
-            const R phi = eA * br * ex;
-            const R dphi = eA * ex * ((qq * sq - pp * B * sp) * ri - br * sig * di * di);
-            const R g = in ? exp(gsig * di) : R(0);
-            const R gx = g * ux, gy = g * uy, gz = g * uz;
-            m[0] += (double)g;
-            m[1] += (double)(g * g);
-            m[2] += (double)gx;
-            m[3] += (double)gy;
-            m[4] += (double)gz;
-            m[5] += (double)(gx * ux);
-            m[6] += (double)(gy * uy);
-            m[7] += (double)(gz * uz);
-            m[8] += (double)(gx * uy);
-            m[9] += (double)(gx * uz);
-            m[10] += (double)(gy * uz);
-            // F_i += phi2'(r) u_ij ; E_i += phi2/2 ; virial, half per ordered pair
-            const R fx = dphi * ux, fy = dphi * uy, fz = dphi * uz;
-            F2x += (double)fx;
-            F2y += (double)fy;
-            F2z += (double)fz;
-            acc[0] += 0.5 * (double)phi;
-            const R hr = R(0.5) * r;
-            vxx += (double)(hr * fx * ux);
-            vyy += (double)(hr * fy * uy);
-            vzz += (double)(hr * fz * uz);
-            vxy += (double)(hr * fx * uy);
-            vxz += (double)(hr * fx * uz);
-            vyz += (double)(hr * fy * uz);
-            if (GRAD) {
-                const R lns = log(sr);
-                acc[10] += 0.5 * (double)((R)sw.eps * br * ex);                   // A
-                acc[11] += 0.5 * (double)(eA * sp * ex);                          // B
-                acc[12] += 0.5 * (double)(eA * B * sp * lns * ex);                // p
-                acc[13] += 0.5 * (double)(-eA * sq * lns * ex);                   // q
-                acc[14] += 0.5 * (double)(phi * sig * sig * di * di);             // a
-                acc[17] += 0.5 * (double)(eA * ex * ((pp * B * sp - qq * sq) / sig + br * r * di * di));  // sigma
-                acc[18] += 0.5 * (double)((R)sw.A * br * ex);                     // epsilon
+        // Terms over the short list, in batches whose indices and positions
+        // are loaded together.
+        for (int k0 = 0; k0 < ns; k0 += kBatchB) {
+            int jb[kBatchB];
+#pragma unroll
+            for (int u = 0; u < kBatchB; ++u) jb[u] = list_entry(p.sl, k0 + u, ns, N, t);
+            double4 xjb[kBatchB];
+#pragma unroll
+            for (int u = 0; u < kBatchB; ++u) xjb[u] = p.xs[jb[u]];
+#pragma unroll
+            for (int u = 0; u < kBatchB; ++u) {
+                if (k0 + u >= ns) break;
+                const double4 xj = xjb[u];
+                const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
+                const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
+                const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
+                const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
+                R r, ri;
+                Fm<R>::dist(ddx * ddx + ddy * ddy + ddz * ddz, r, ri);
+                const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
+                // inside the cutoff in FP64 may round to r >= rc in the term
+                // precision; the terms vanish there, so they are zeroed
+                const R den = r - rc;
+                const bool in = den < R(0);
+                const R di = in ? Fm<R>::rcp(den) : R(0);
+                const R sr = sig * ri;
+                const R sp = powi_or_pow(sr, sw.ip, pp);
+                const R sq = powi_or_pow(sr, sw.iq, qq);
+                const R ex = in ? Fm<R>::exp(sig * di) : R(0);
+                const R br = B * sp - sq;
+                const R phi = eA * br * ex;
+                const R dphi = eA * ex * ((qq * sq - pp * B * sp) * ri - br * sig * di * di);
+                const R g = in ? Fm<R>::exp(gsig * di) : R(0);
+                const R gx = g * ux, gy = g * uy, gz = g * uz;
+                m[0] += (double)g;
+                m[1] += (double)(g * g);
+                m[2] += (double)gx;
+                m[3] += (double)gy;
+                m[4] += (double)gz;
+                m[5] += (double)(gx * ux);
+                m[6] += (double)(gy * uy);
+                m[7] += (double)(gz * uz);
+                m[8] += (double)(gx * uy);
+                m[9] += (double)(gx * uz);
+                m[10] += (double)(gy * uz);
+                // F_i += phi2'(r) u_ij ; E_i += phi2/2 ; virial, half per ordered pair
+                const R fx = dphi * ux, fy = dphi * uy, fz = dphi * uz;
+                F2x += (double)fx;
+                F2y += (double)fy;
+                F2z += (double)fz;
+                acc[0] += 0.5 * (double)phi;
+                const R hr = R(0.5) * r;
+                vxx += (double)(hr * fx * ux);
+                vyy += (double)(hr * fy * uy);
+                vzz += (double)(hr * fz * uz);
+                vxy += (double)(hr * fx * uy);
+                vxz += (double)(hr * fx * uz);
+                vyz += (double)(hr * fy * uz);
+                if (GRAD) {
+                    const R lns = Fm<R>::log(sr);
+                    acc[10] += 0.5 * (double)((R)sw.eps * br * ex);                   // A
+                    acc[11] += 0.5 * (double)(eA * sp * ex);                          // B
+                    acc[12] += 0.5 * (double)(eA * B * sp * lns * ex);                // p
+                    acc[13] += 0.5 * (double)(-eA * sq * lns * ex);                   // q
+                    acc[14] += 0.5 * (double)(phi * sig * sig * di * di);             // a
+                    acc[17] += 0.5 * (double)(eA * ex * ((pp * B * sp - qq * sq) / sig + br * r * di * di));  // sigma
+                    acc[18] += 0.5 * (double)((R)sw.A * br * ex);                     // epsilon
+                }
             }
         }
         acc[1] = vxx;
@@ -709,7 +802,7 @@ __global__ void __launch_bounds__(256) k_pass1(Ctl c, DevPtrs p, SwParams sw)
         mo.v[11] = R(0);
         reinterpret_cast<Mom<R> *>(p.mom)[t] = mo;
         if (nin > kMaxShort) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
-        p.nnb[t] = nin < kMaxShort ? nin : kMaxShort;
+        p.nnb[t] = ns;
         p.fs[t] = make_double4(F2x, F2y, F2z, 0.0);
         p.e_s[t] = acc[0] + acc[19];
     }
@@ -950,7 +1043,7 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
 }
 
 template <typename R, bool GRAD>
-__global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass2(Ctl c, DevPtrs p, SwParams sw)
 {
     constexpr int NV = 24;  // -, virial 9, dtheta 9, U_ref, K, noise 3
     double acc[NV];
@@ -975,47 +1068,55 @@ __global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
         double F3x = 0, F3y = 0, F3z = 0;
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
         double gg = 0, ga = 0, gs = 0;  // sum H g dln g/d(gamma, a, sigma)
-        // the neighbours within rc that pass 1 found at these positions
+        // the neighbours within rc that pass 1 found at these positions, in
+        // batches whose indices, positions and moments are loaded together
         const int cnt = p.nnb[t];
-        int jn = cnt > 0 ? p.sl[t] : t;
-        int jnn = cnt > 1 ? p.sl[N + t] : t;
-        double4 xn = p.xs[jn];
-        for (int k = 0; k < cnt; ++k) {
-            const int j = jn;
-            const double4 xj = xn;
-            jn = jnn;
-            xn = p.xs[jn];
-            jnn = k + 2 < cnt ? p.sl[(int64_t)(k + 2) * N + t] : t;
-            const Mom<R> mJ = mom[j];
-            const double dx = min_image(xj.x - xa.x, box[0], ibox[0]);
-            const double dy = min_image(xj.y - xa.y, box[1], ibox[1]);
-            const double dz = min_image(xj.z - xa.z, box[2], ibox[2]);
-            const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
-            const R r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            const R ri = R(1) / r;
-            const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
-            const R den = r - rc;
-            const bool in = den < R(0);
-            const R di = in ? R(1) / den : R(0);
-            const R g = in ? exp(gsig * di) : R(0);
-            const R dg = -g * gsig * di * di;
-            R tA[3], tJ[3], HA, HJ;
-            d_e3<R>(mA.v, ux, uy, uz, g, dg, ri, c0, hle, tA, HA);
-            d_e3<R>(mJ.v, -ux, -uy, -uz, g, dg, ri, c0, hle, tJ, HJ);
-            F3x += (double)tA[0] - (double)tJ[0];
-            F3y += (double)tA[1] - (double)tJ[1];
-            F3z += (double)tA[2] - (double)tJ[2];
-            vxx += (double)(tA[0] * ddx);
-            vyy += (double)(tA[1] * ddy);
-            vzz += (double)(tA[2] * ddz);
-            vxy += (double)(R(0.5) * (tA[0] * ddy + tA[1] * ddx));
-            vxz += (double)(R(0.5) * (tA[0] * ddz + tA[2] * ddx));
-            vyz += (double)(R(0.5) * (tA[1] * ddz + tA[2] * ddy));
-            if (GRAD) {
-                const R hg = HA * g;
-                gg += (double)(hg * (R)sw.sig * di);
-                ga += (double)(hg * gsig * (R)sw.sig * di * di);
-                gs += (double)(hg * (R)sw.gam * r * di * di);
+        for (int k0 = 0; k0 < cnt; k0 += kBatch2) {
+            int jb[kBatch2];
+#pragma unroll
+            for (int u = 0; u < kBatch2; ++u) jb[u] = list_entry(p.sl, k0 + u, cnt, N, t);
+            double4 xjb[kBatch2];
+            Mom<R> mjb[kBatch2];
+#pragma unroll
+            for (int u = 0; u < kBatch2; ++u) {
+                xjb[u] = p.xs[jb[u]];
+                mjb[u] = mom[jb[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch2; ++u) {
+                if (k0 + u >= cnt) break;
+                const double4 xj = xjb[u];
+                const Mom<R> &mJ = mjb[u];
+                const double dx = min_image(xj.x - xa.x, box[0], ibox[0]);
+                const double dy = min_image(xj.y - xa.y, box[1], ibox[1]);
+                const double dz = min_image(xj.z - xa.z, box[2], ibox[2]);
+                const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
+                R r, ri;
+                Fm<R>::dist(ddx * ddx + ddy * ddy + ddz * ddz, r, ri);
+                const R ux = ddx * ri, uy = ddy * ri, uz = ddz * ri;
+                const R den = r - rc;
+                const bool in = den < R(0);
+                const R di = in ? Fm<R>::rcp(den) : R(0);
+                const R g = in ? Fm<R>::exp(gsig * di) : R(0);
+                const R dg = -g * gsig * di * di;
+                R tA[3], tJ[3], HA, HJ;
+                d_e3<R>(mA.v, ux, uy, uz, g, dg, ri, c0, hle, tA, HA);
+                d_e3<R>(mJ.v, -ux, -uy, -uz, g, dg, ri, c0, hle, tJ, HJ);
+                F3x += (double)tA[0] - (double)tJ[0];
+                F3y += (double)tA[1] - (double)tJ[1];
+                F3z += (double)tA[2] - (double)tJ[2];
+                vxx += (double)(tA[0] * ddx);
+                vyy += (double)(tA[1] * ddy);
+                vzz += (double)(tA[2] * ddz);
+                vxy += (double)(R(0.5) * (tA[0] * ddy + tA[1] * ddx));
+                vxz += (double)(R(0.5) * (tA[0] * ddz + tA[2] * ddx));
+                vyz += (double)(R(0.5) * (tA[1] * ddz + tA[2] * ddy));
+                if (GRAD) {
+                    const R hg = HA * g;
+                    gg += (double)(hg * (R)sw.sig * di);
+                    ga += (double)(hg * gsig * (R)sw.sig * di * di);
+                    gs += (double)(hg * (R)sw.gam * r * di * di);
+                }
             }
         }
         acc[1] = vxx;
@@ -1039,9 +1140,8 @@ __global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
         F.z += F3z;
         p.fs[t] = F;
         // Einstein reference (Frenkel-Ladd systems)
-        double4 x0 = make_double4(0, 0, 0, 0);
+        const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
         if (d.mode == MODE_FL) {
-            x0 = p.x0s[t];
             const double ex = xa.x - x0.x, ey = xa.y - x0.y, ez = xa.z - x0.z;
             acc[19] = 0.5 * d.k_spring * (ex * ex + ey * ey + ez * ez);
         }
@@ -1055,10 +1155,12 @@ __global__ void __launch_bounds__(256) k_pass2(Ctl c, DevPtrs p, SwParams sw)
             p.vs[t] = v;
         }
         acc[20] = d.mvv2e_m * (v.x * v.x + v.y * v.y + v.z * v.z);
-        // normals of the next O step, for its zero-sum correction
+        // normals of the next O step: stored for it, and summed for its
+        // zero-sum correction
         if (o_step_on(d)) {
             double z[3];
             normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)(p.perm[t] - d.off), z);
+            p.zs[t] = make_double4(z[0], z[1], z[2], 0.0);
             acc[21] = z[0];
             acc[22] = z[1];
             acc[23] = z[2];
@@ -1163,6 +1265,12 @@ hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, in
             hipLaunchKernelGGL(k_rb_list, dim3(4 * kWorkGrid), dim3(256), 0, s, c, p, sw, (block + 7) / 8);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_noise(const Ctl &c, const DevPtrs &p, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_noise, tile_grid(c), dim3(block), 0, s, c, p);
     return hipGetLastError();
 }
 
