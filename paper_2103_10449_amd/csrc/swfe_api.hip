@@ -29,7 +29,7 @@ constexpr double kDefaultSkin = 0.5;                                    // A
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s, zs;
+    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s, zs, xf;
     size_t perm, tperm, norder, rank, cellid, nnb, sl, cell_count, cell_start, nl, nl_cnt, mom, e_s;
     size_t part1, part2, disp_max, work, n_work, desc, state, tiles, groups, log, strain, total;
 };
@@ -243,6 +243,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.tfs = take(d4 * n);
     L.tx0s = take(d4 * n);
     L.zs = take(d4 * n);
+    L.xf = take(sizeof(float4) * n);
     L.perm = take(4 * n);
     L.tperm = take(4 * n);
     L.norder = take(4 * n);
@@ -492,6 +493,7 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     q.tfs = (double4 *)(w + L.tfs);
     q.tx0s = (double4 *)(w + L.tx0s);
     q.zs = (double4 *)(w + L.zs);
+    q.xf = (float4 *)(w + L.xf);
     q.perm = (int32_t *)(w + L.perm);
     q.tperm = (int32_t *)(w + L.tperm);
     q.norder = (int32_t *)(w + L.norder);

@@ -112,6 +112,7 @@ struct DevPtrs {
     double4 *xs, *vs, *fs, *x0s, *xb;     // positions, velocities, F_int, anchors, build positions
     double4 *txs, *tvs, *tfs, *tx0s;      // permutation staging
     double4 *zs;                          // normals of the next O step, sorted order
+    float4 *xf;                           // FP32 positions wrapped into the box (list filter)
     int32_t *perm, *tperm, *norder, *rank, *cellid;  // norder: staged cell index
     int32_t *cell_count, *cell_start;
     int32_t *nl, *nl_cnt;                 // Verlet list [kMaxList][n_total] of sorted positions

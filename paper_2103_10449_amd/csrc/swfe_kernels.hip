@@ -119,6 +119,15 @@ __device__ __forceinline__ double min_image(double d, double box, double ibox)
     return d - box * rint(d * ibox);
 }
 
+// FP32 copy of a position, wrapped into [0, box) with the box the force
+// passes use for the minimum image (the wrap shifts by whole boxes, which
+// the minimum image removes again).  The list filter reads it.
+__device__ __forceinline__ float4 pos_f32(const double4 &x, const double box[3], const double ibox[3])
+{
+    return make_float4((float)(x.x - box[0] * floor(x.x * ibox[0])), (float)(x.y - box[1] * floor(x.y * ibox[1])),
+                       (float)(x.z - box[2] * floor(x.z * ibox[2])), 0.0f);
+}
+
 // Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: three normals per
 // (step, atom) with key (seed, stream).
 __device__ __forceinline__ void normals3(uint64_t seed, uint64_t stream, uint64_t step,
@@ -236,7 +245,11 @@ __global__ void __launch_bounds__(256) k_gather(Ctl c, DevPtrs p, int with_f)
     const int64_t N = c.n_total;
     const int t = tile.start + threadIdx.x;
     const int i = p.perm[t];
-    p.xs[t] = make_double4(p.x[i] * st.pscale[0], p.x[N + i] * st.pscale[1], p.x[2 * N + i] * st.pscale[2], 0.0);
+    const double4 x = make_double4(p.x[i] * st.pscale[0], p.x[N + i] * st.pscale[1], p.x[2 * N + i] * st.pscale[2], 0.0);
+    double box[3], ibox[3];
+    eff_box(st, box, ibox);
+    p.xs[t] = x;
+    p.xf[t] = pos_f32(x, box, ibox);
     p.vs[t] = make_double4(p.v[i], p.v[N + i], p.v[2 * N + i], 0.0);
     if (with_f) p.fs[t] = make_double4(p.f[i], p.f[N + i], p.f[2 * N + i], 0.0);
     if (p.x0) p.x0s[t] = make_double4(p.x0[i], p.x0[N + i], p.x0[2 * N + i], 0.0);
@@ -335,6 +348,9 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p)
             x.z = x.z * st.grow + (v.z * hdt) * st.psi;
             p.xs[t] = x;
             p.vs[t] = v;
+            double box[3], ibox[3];
+            eff_box(st, box, ibox);
+            p.xf[t] = pos_f32(x, box, ibox);
         }
         if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z))) atomicOr(&p.state[sys].err, ERR_NONFINITE);
         const double4 b = p.xb[t];
@@ -513,7 +529,10 @@ __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
         for (int j = b; j < e; ++j) rank += p.tperm[j] < key ? 1 : 0;
         const int s = b + rank;
         const double4 x = p.txs[i];
+        double box[3], ibox[3];
+        eff_box(p.state[sys], box, ibox);
         p.xs[s] = x;
+        p.xf[s] = pos_f32(x, box, ibox);
         p.xb[s] = x;
         p.vs[s] = p.tvs[i];
         p.fs[s] = p.tfs[i];
@@ -644,8 +663,13 @@ struct Fm<double> {
 };
 
 // Gather batch sizes: list candidates (filter), short-list neighbours in
-// pass 1 and in pass 2.
-constexpr int kBatchA = 8, kBatchB = 4, kBatch2 = 4;
+// pass 1 and in pass 2 (smaller where the registers are needed elsewhere).
+constexpr int kBatchA = 8;
+template <typename R, bool GRAD>
+struct Batch {
+    static constexpr int B = GRAD ? 2 : 4;
+    static constexpr int P2 = sizeof(R) == 4 ? 4 : 2;
+};
 
 // Entry k of atom t's list ([row][n_total] layout, n valid rows, n >= 1).
 // Rows past the end read the last valid row (no branch around the load) and
@@ -681,23 +705,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // It is cheap per candidate, so lanes whose candidates are mostly
         // outside rc do not hold the wave in the term evaluation below.
         int nin = 0;
-        // batches of kBatchA candidates: all their indices, then all their
-        // positions, are in flight together
-        for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
-            int jb[kBatchA];
+        {
+            // Conservative FP32 test: the rounding of the wrapped FP32
+            // coordinates moves d^2 by far less than the margin, so every
+            // pair within rc passes; the exact FP64 test follows in the
+            // term loop, which also drops the few extra pairs.
+            const float4 xif = p.xf[t];
+            const float bx = (float)box[0], by = (float)box[1], bz = (float)box[2];
+            const float ibx = (float)ibox[0], iby = (float)ibox[1], ibz = (float)ibox[2];
+            const double bmax = fmax(box[0], fmax(box[1], box[2]));
+            const float cut2 = (float)(sw.rc2 * (1.0 + 1e-3) + 32.0 * sw.rc * bmax * 1.1920928955078125e-7);
+            // batches of kBatchA candidates: all their indices, then all
+            // their positions, are in flight together
+            for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
+                int jb[kBatchA];
 #pragma unroll
-            for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
-            double4 xj[kBatchA];
+                for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
+                float4 xj[kBatchA];
 #pragma unroll
-            for (int u = 0; u < kBatchA; ++u) xj[u] = p.xs[jb[u]];
+                for (int u = 0; u < kBatchA; ++u) xj[u] = p.xf[jb[u]];
 #pragma unroll
-            for (int u = 0; u < kBatchA; ++u) {
-                const double dx = min_image(xj[u].x - xi.x, box[0], ibox[0]);
-                const double dy = min_image(xj[u].y - xi.y, box[1], ibox[1]);
-                const double dz = min_image(xj[u].z - xi.z, box[2], ibox[2]);
-                if (k0 + u < cnt && dx * dx + dy * dy + dz * dz < sw.rc2) {
-                    if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = jb[u];
-                    ++nin;
+                for (int u = 0; u < kBatchA; ++u) {
+                    float dx = xj[u].x - xif.x, dy = xj[u].y - xif.y, dz = xj[u].z - xif.z;
+                    dx -= bx * rintf(dx * ibx);
+                    dy -= by * rintf(dy * iby);
+                    dz -= bz * rintf(dz * ibz);
+                    if (k0 + u < cnt && dx * dx + dy * dy + dz * dz < cut2) {
+                        if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = jb[u];
+                        ++nin;
+                    }
                 }
             }
         }
@@ -709,6 +745,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
         // Terms over the short list, in batches whose indices and positions
         // are loaded together.
+        int nkeep = 0;
+        constexpr int kBatchB = Batch<R, GRAD>::B;
         for (int k0 = 0; k0 < ns; k0 += kBatchB) {
             int jb[kBatchB];
 #pragma unroll
@@ -723,6 +761,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
                 const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
                 const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
+                // exact membership; kept entries move down over dropped ones
+                // (an entry is rewritten only after it has been read)
+                if (!(dx * dx + dy * dy + dz * dz < sw.rc2)) continue;
+                if (nkeep != k0 + u) p.sl[(int64_t)nkeep * N + t] = jb[u];
+                ++nkeep;
                 const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
                 R r, ri;
                 Fm<R>::dist(ddx * ddx + ddy * ddy + ddz * ddz, r, ri);
@@ -802,7 +845,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         mo.v[11] = R(0);
         reinterpret_cast<Mom<R> *>(p.mom)[t] = mo;
         if (nin > kMaxShort) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
-        p.nnb[t] = ns;
+        p.nnb[t] = nkeep;
         p.fs[t] = make_double4(F2x, F2y, F2z, 0.0);
         p.e_s[t] = acc[0] + acc[19];
     }
@@ -1064,6 +1107,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const double4 xa = p.xs[t];
         const Mom<R> *mom = reinterpret_cast<const Mom<R> *>(p.mom);
         const Mom<R> mA = mom[t];
+        // per-atom operands of the tail, in flight during the gather
+        const double4 F2 = p.fs[t];
+        const double4 v0 = p.vs[t];
+        const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
+        const int atom = p.perm[t] - d.off;
         const R rc = (R)sw.rc, gsig = (R)(sw.gam * sw.sig), c0 = (R)sw.cos0, hle = (R)(0.5 * sw.le);
         double F3x = 0, F3y = 0, F3z = 0;
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
@@ -1071,6 +1119,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // the neighbours within rc that pass 1 found at these positions, in
         // batches whose indices, positions and moments are loaded together
         const int cnt = p.nnb[t];
+        constexpr int kBatch2 = Batch<R, GRAD>::P2;
         for (int k0 = 0; k0 < cnt; k0 += kBatch2) {
             int jb[kBatch2];
 #pragma unroll
@@ -1134,19 +1183,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             acc[16] = hl * gg;  // gamma
             acc[17] = hl * gs;  // sigma
         }
-        double4 F = p.fs[t];
+        double4 F = F2;
         F.x += F3x;
         F.y += F3y;
         F.z += F3z;
         p.fs[t] = F;
         // Einstein reference (Frenkel-Ladd systems)
-        const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
         if (d.mode == MODE_FL) {
             const double ex = xa.x - x0.x, ey = xa.y - x0.y, ez = xa.z - x0.z;
             acc[19] = 0.5 * d.k_spring * (ex * ex + ey * ey + ez * ez);
         }
         // final half kick of a dynamics step, then the kinetic energy
-        double4 v = p.vs[t];
+        double4 v = v0;
         if (c.in_step && d.mode != MODE_FORCE) {
             const double ka = (0.5 * c.dt) * d.acc;
             v.x = v.x * st.decay + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring) * st.phi;
@@ -1159,7 +1207,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // zero-sum correction
         if (o_step_on(d)) {
             double z[3];
-            normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)(p.perm[t] - d.off), z);
+            normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)atom, z);
             p.zs[t] = make_double4(z[0], z[1], z[2], 0.0);
             acc[21] = z[0];
             acc[22] = z[1];
