@@ -234,7 +234,8 @@ int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream);
 
 /* Measurement: run n_steps eager dynamics steps with HIP events recorded on
  * the stream between the kernels of each step; ms[0..8] receive the summed
- * durations of integrate, rebuild count, rebuild scan, rebuild scatter,
+ * durations of integrate, rebuild count (with the rebuild decision),
+ * rebuild scan, rebuild scatter,
  * rebuild order, rebuild list, pass1, pass2 and finalize (ms, host array of
  * 9).  Synchronises.  The steps advance the systems like swfe_step_switched. */
 #define SWFE_NUM_KERNELS 9

@@ -11,7 +11,7 @@ constexpr int kMaxList = 64;       // Verlet-list capacity per atom (within rc +
 constexpr int kMaxShort = 48;      // neighbours within rc per atom (pass 1 -> pass 2)
 constexpr int kSortThreads = 1024; // threads of the per-system sort workgroup
 constexpr int kNumKernels = 9;     // launches of one dynamics step (for profiling)
-constexpr int kRebuildStages = 5;  // rebuild stages (the first is two launches)
+constexpr int kRebuildStages = 5;  // rebuild stages
 constexpr int kWorkGrid = 512;     // blocks of the work-list rebuild kernels
 
 // Per-tile partial sums of the two force passes (fixed slots).

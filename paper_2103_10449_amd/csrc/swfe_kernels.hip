@@ -6,13 +6,14 @@
 // caller's atom index at sorted position t.  Neighbour lists hold sorted
 // positions, so neighbours of a tile are nearby in memory.
 //
-// One dynamics step is ten launches over all systems at once:
+// One dynamics step is nine launches over all systems at once:
 //   integrate    B kick, A drift, O Langevin, A drift; per-tile maximum
 //                displacement since the last list build
-//   rebuild 0-4  (only systems whose list may miss a pair do any work)
-//                0 decide:  one block lists the tiles of stale systems;
-//                  count:   cell index and rank within the cell
-//                1 scan:    per-system cell starts
+//   rebuild 0-4  (only systems whose list may miss a pair do any work; the
+//                decision is taken per block from the displacement bound)
+//                0 count:   cell index and rank within the cell
+//                1 scan:    per-system cell starts, and the tiles of the
+//                           later stages' work list
 //                2 scatter: atom data into its cell's segment (staging)
 //                3 order:   in-cell order by the caller's atom index
 //                4 list:    Verlet list within rc + skin from the 27 cells
@@ -290,6 +291,20 @@ __global__ void __launch_bounds__(256) k_scatter(Ctl c, DevPtrs p, int what)
     }
 }
 
+// Cell of an atom at its current position and its rank among the atoms
+// counted into that cell (the order of the ranks is fixed later).
+__device__ __forceinline__ void bin_atom(const DevPtrs &p, const SwParams &sw, const SysDesc &d,
+                                         const SysState &st, int t, const double4 &x)
+{
+    double box[3], ibox[3];
+    int nc[3];
+    eff_box(st, box, ibox);
+    cell_grid(d, box, sw.rc + d.skin, nc);
+    const int cell = cell_of_pos(x, ibox, nc);
+    p.cellid[t] = cell;
+    p.rank[t] = atomicAdd(&p.cell_count[d.cell_base + cell], 1);
+}
+
 // Normals of the next O step for every atom in the current order (after a
 // list build outside a step reorders the atoms).
 __global__ void __launch_bounds__(256) k_fill_noise(Ctl c, DevPtrs p)
@@ -311,7 +326,7 @@ __global__ void __launch_bounds__(256) k_fill_noise(Ctl c, DevPtrs p)
 // A half drift with isotropic box scaling, O Langevin step with zero-sum
 // noise, A half drift.  Then the displacement from the list-build position
 // (scaled with the box) for the rebuild test.
-__global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p)
+__global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw)
 {
     const int ti = tile_of_block(c);
     if (ti < 0) return;
@@ -386,72 +401,29 @@ __device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, i
     return 2.0 * sqrt(m) + (sw.rc + d.skin) * shrink > d.skin;
 }
 
-// One block: the rebuild decision of every system and the compact list of
-// the tiles to rebuild (p.work[0..n_work)), so that the rebuild stages cost
-// almost nothing on steps where no list is stale.
-__global__ void __launch_bounds__(256) k_rb_decide(Ctl c, DevPtrs p, SwParams sw)
-{
-    __shared__ int scan[256];
-    int base = 0;
-    for (int s0 = 0; s0 < c.n_sys; s0 += 256) {
-        const int sys = s0 + (int)threadIdx.x;
-        int nt = 0;
-        bool rb = false;
-        if (sys < c.n_sys) {
-            rb = list_stale(c, p, sw, sys);
-            SysState &st = p.state[sys];
-            st.rb = rb ? 1 : 0;
-            // clear the slot the next step's integrate fills (both on a forced build)
-            p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
-            if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
-            if (rb) nt = p.desc[sys].tile_end - p.desc[sys].tile_begin;
-        }
-        scan[threadIdx.x] = nt;
-        __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            const int add = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
-            __syncthreads();
-            scan[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (rb) {
-            const int at = base + scan[threadIdx.x] - nt;
-            const int tb = p.desc[sys].tile_begin;
-            for (int q = 0; q < nt; ++q) p.work[at + q] = tb + q;
-        }
-        base += scan[255];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) p.n_work[0] = base;
-}
-
+// Binning of the atoms of every system whose list is stale (each block
+// takes the decision for its tile's system; the scan stage takes the same
+// decision from the same inputs).  The rebuild work list starts empty.
 __global__ void __launch_bounds__(256) k_rb_count(Ctl c, DevPtrs p, SwParams sw)
 {
-    const int n_work = p.n_work[0];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const Tile tile = p.tiles[p.work[w]];
-        if ((int)threadIdx.x >= tile.count) continue;
-        const int sys = tile.sys;
-        const SysDesc &d = p.desc[sys];
-        const SysState &st = p.state[sys];
-        double box[3], ibox[3];
-        int nc[3];
-        eff_box(st, box, ibox);
-        cell_grid(d, box, sw.rc + d.skin, nc);
-        const int t = tile.start + threadIdx.x;
-        const int cell = cell_of_pos(p.xs[t], ibox, nc);
-        p.cellid[t] = cell;
-        p.rank[t] = atomicAdd(&p.cell_count[d.cell_base + cell], 1);
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.n_work[0] = 0;
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    if (!list_stale(c, p, sw, tile.sys)) return;
+    if ((int)threadIdx.x >= tile.count) return;
+    const int t = tile.start + threadIdx.x;
+    bin_atom(p, sw, p.desc[tile.sys], p.state[tile.sys], t, p.xs[t]);
 }
 
-// One workgroup per system: exclusive scan of the cell counts into cell
-// starts (sorted positions); the counts are cleared for the next build.
+// One workgroup per system: the rebuild decision; for a stale list the
+// exclusive scan of the cell counts into cell starts (sorted positions),
+// the counts cleared for the next binning, and the system's tiles appended
+// to the work list of the later stages.
 __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwParams sw)
 {
     const int sys = blockIdx.x;
     SysState &st = p.state[sys];
-    if (!st.rb) return;
     const SysDesc &d = p.desc[sys];
     double box[3], ibox[3];
     int nc3[3];
@@ -459,8 +431,22 @@ __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwPa
     cell_grid(d, box, sw.rc + d.skin, nc3);
     const int nc = nc3[0] * nc3[1] * nc3[2];
     int32_t *cnt = p.cell_count + d.cell_base;
+    const int tid = threadIdx.x;
+    __shared__ int rb_s, at_s;
+    if (tid == 0) {
+        const bool rb = list_stale(c, p, sw, sys);
+        st.rb = rb ? 1 : 0;
+        // clear the slot the next step's integrate fills (both on a forced build)
+        p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
+        if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
+        rb_s = rb ? 1 : 0;
+        at_s = rb ? atomicAdd(&p.n_work[0], d.tile_end - d.tile_begin) : 0;
+    }
+    __syncthreads();
+    if (!rb_s) return;
+    for (int q = tid; q < d.tile_end - d.tile_begin; q += kSortThreads) p.work[at_s + q] = d.tile_begin + q;
     int32_t *start = p.cell_start + d.cell_base + sys;  // nc + 1 entries
-    const int off = (int)d.off, n = (int)d.n, tid = threadIdx.x;
+    const int off = (int)d.off, n = (int)d.n;
 
     __shared__ int32_t part[kSortThreads];
     const int per = (nc + kSortThreads - 1) / kSortThreads;
@@ -1022,7 +1008,16 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
         double a = 0.0;
         if (k < 2 * kNumPart) {
             const double *src = k < kNumPart ? p.part1 + k : p.part2 + (k - kNumPart);
-            for (int t = d.tile_begin + j; t < d.tile_end; t += nj) a += src[(int64_t)t * kNumPart];
+            // eight independent loads in flight per round, summed in a fixed order
+            int t = d.tile_begin + j;
+            for (; t + 7 * nj < d.tile_end; t += 8 * nj) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(t + u * nj) * kNumPart];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a += v[u];
+            }
+            for (; t < d.tile_end; t += nj) a += src[(int64_t)t * kNumPart];
         }
         red[j][k] = a;
         __syncthreads();
@@ -1294,7 +1289,7 @@ hipError_t launch_scatter(const Ctl &c, const DevPtrs &p, int block, int what, h
 hipError_t launch_integrate(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block, hipStream_t s)
 {
     (void)sw;
-    hipLaunchKernelGGL(k_integrate, tile_grid(c), dim3(block), 0, s, c, p);
+    hipLaunchKernelGGL(k_integrate, tile_grid(c), dim3(block), 0, s, c, p, sw);
     return hipGetLastError();
 }
 
@@ -1302,10 +1297,7 @@ hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, in
                           hipStream_t s)
 {
     switch (stage) {
-        case 0:
-            hipLaunchKernelGGL(k_rb_decide, dim3(1), dim3(256), 0, s, c, p, sw);
-            hipLaunchKernelGGL(k_rb_count, dim3(kWorkGrid), dim3(block), 0, s, c, p, sw);
-            break;
+        case 0: hipLaunchKernelGGL(k_rb_count, tile_grid(c), dim3(block), 0, s, c, p, sw); break;
         case 1: hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw); break;
         case 2: hipLaunchKernelGGL(k_rb_scatter, dim3(kWorkGrid), dim3(block), 0, s, c, p); break;
         case 3: hipLaunchKernelGGL(k_rb_order, dim3(kWorkGrid), dim3(block), 0, s, c, p); break;
