@@ -255,7 +255,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.nl = take(4 * n * kMaxList);
     L.nl_cnt = take(4 * n);
     L.sl = take(4 * n * kMaxShort);
-    L.mom = take(8 * 12 * n);
+    L.mom = take(8 * 9 * n);
     L.e_s = take(8 * n);
     L.part1 = take(8 * (size_t)tiles * kNumPart);
     L.part2 = take(8 * (size_t)tiles * kNumPart);

@@ -118,7 +118,7 @@ struct DevPtrs {
     int32_t *nl, *nl_cnt;                 // Verlet list [kMaxList][n_total] of sorted positions
     int32_t *nnb;                         // neighbours within rc per atom (last pass 1)
     int32_t *sl;                          // [kMaxShort][n_total] those neighbours (sorted positions)
-    void *mom;                            // [n_total][12] moments in term precision
+    void *mom;                            // [n_total][9] moments (v, M) in term precision
     double *e_s;                          // per-atom energy, sorted order
     double *part1, *part2;                // [n_tiles][kNumPart]
     int32_t *work, *n_work;               // tiles to rebuild in this step, and their count

@@ -69,6 +69,15 @@ __device__ __forceinline__ int tile_of_block(const Ctl &c)
     return t < c.n_tiles ? t : -1;
 }
 
+// General power, kept out of line: it is only reached for non-integer
+// exponents (parameter derivatives by finite differences).
+template <typename R>
+__device__ __noinline__ R pow_general(R s, R p)
+{
+    return pow(s, p);
+}
+
+// s^p with ip = p when p is a non-negative integer (ip < 0 otherwise).
 template <typename R>
 __device__ __forceinline__ R powi_or_pow(R s, int ip, R p)
 {
@@ -77,7 +86,7 @@ __device__ __forceinline__ R powi_or_pow(R s, int ip, R p)
         for (int k = 0; k < ip; ++k) r *= s;
         return r;
     }
-    return pow(s, p);
+    return pow_general(s, p);
 }
 
 __device__ __forceinline__ void eff_box(const SysState &st, double box[3], double ibox[3])
@@ -612,9 +621,12 @@ __global__ void __launch_bounds__(256) k_rb_list(Ctl c, DevPtrs p, SwParams sw, 
 // Pair terms (energy, force, virial, parameter derivative: half per ordered
 // pair), the three-body moments and the atom's own three-body energy.  R is
 // the arithmetic type of the terms; sums are FP64.
+// Moments a neighbour's gather needs, in term precision: v (3), then M
+// (xx, yy, zz, xy, xz, yz).  s = tr M is not stored (|u| = 1), and q is not
+// needed by the gather.
 template <typename R>
-struct alignas(16) Mom {
-    R v[12];
+struct Mom {
+    R v[9];
 };
 
 // Term arithmetic.  FP32 terms use the hardware reciprocal, reciprocal
@@ -827,8 +839,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         }
         Mom<R> mo;
 #pragma unroll
-        for (int k = 0; k < 11; ++k) mo.v[k] = (R)m[k];
-        mo.v[11] = R(0);
+        for (int k = 0; k < 9; ++k) mo.v[k] = (R)m[k + 2];
         reinterpret_cast<Mom<R> *>(p.mom)[t] = mo;
         if (nin > kMaxShort) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
         p.nnb[t] = nkeep;
@@ -842,13 +853,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 // d E3_c / d r_cj for a centre with moments (s, q, v, M) and a neighbour at
 // unit vector u, distance r, g = g(r), dg = g'(r):
 //   (le/2) [ dg H u + (4 g / r) ((M u - (u.M.u) u) - c0 (v - (v.u) u)) ],
-//   H = 2 u.M.u - 4 c0 v.u + 2 c0^2 s - 2 (1 - c0)^2 g.
+//   H = 2 u.M.u - 4 c0 v.u + 2 c0^2 s - 2 (1 - c0)^2 g,
+// evaluated as alpha u + beta (M u - c0 v) with
+//   alpha = (le/2) (dg H - (4 g / r) (u.M.u - c0 v.u)),  beta = (le/2) 4 g / r.
+// hdg = (le/2) dg and hb = beta are shared by both ends of a pair.
 template <typename R>
-__device__ __forceinline__ void d_e3(const R *mom, R ux, R uy, R uz, R g, R dg, R ri, R c0, R hle,
-                                     R out[3], R &H)
+__device__ __forceinline__ void d_e3(const R *mom, R ux, R uy, R uz, R g, R hdg, R hb, R c0, R out[3], R &H)
 {
-    const R s = mom[0], vx = mom[2], vy = mom[3], vz = mom[4];
-    const R Mxx = mom[5], Myy = mom[6], Mzz = mom[7], Mxy = mom[8], Mxz = mom[9], Myz = mom[10];
+    const R vx = mom[0], vy = mom[1], vz = mom[2];
+    const R Mxx = mom[3], Myy = mom[4], Mzz = mom[5], Mxy = mom[6], Mxz = mom[7], Myz = mom[8];
+    const R s = Mxx + Myy + Mzz;  // sum g (u.u = 1)
     const R mux = Mxx * ux + Mxy * uy + Mxz * uz;
     const R muy = Mxy * ux + Myy * uy + Myz * uz;
     const R muz = Mxz * ux + Myz * uy + Mzz * uz;
@@ -856,11 +870,10 @@ __device__ __forceinline__ void d_e3(const R *mom, R ux, R uy, R uz, R g, R dg, 
     const R vu = vx * ux + vy * uy + vz * uz;
     const R omc = R(1) - c0;
     H = R(2) * umu - R(4) * c0 * vu + R(2) * c0 * c0 * s - R(2) * omc * omc * g;
-    const R a = dg * H;
-    const R b = R(4) * g * ri;
-    out[0] = hle * (a * ux + b * ((mux - umu * ux) - c0 * (vx - vu * ux)));
-    out[1] = hle * (a * uy + b * ((muy - umu * uy) - c0 * (vy - vu * uy)));
-    out[2] = hle * (a * uz + b * ((muz - umu * uz) - c0 * (vz - vu * uz)));
+    const R alpha = hdg * H - hb * (umu - c0 * vu);
+    out[0] = alpha * ux + hb * (mux - c0 * vx);
+    out[1] = alpha * uy + hb * (muy - c0 * vy);
+    out[2] = alpha * uz + hb * (muz - c0 * vz);
 }
 
 // ---- per-group reduction and scalar update (last tile of a group) --------
@@ -1142,13 +1155,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 const bool in = den < R(0);
                 const R di = in ? Fm<R>::rcp(den) : R(0);
                 const R g = in ? Fm<R>::exp(gsig * di) : R(0);
-                const R dg = -g * gsig * di * di;
+                const R hdg = -hle * g * gsig * di * di;  // (le/2) g'(r)
+                const R hb = R(4) * hle * g * ri;
                 R tA[3], tJ[3], HA, HJ;
-                d_e3<R>(mA.v, ux, uy, uz, g, dg, ri, c0, hle, tA, HA);
-                d_e3<R>(mJ.v, -ux, -uy, -uz, g, dg, ri, c0, hle, tJ, HJ);
-                F3x += (double)tA[0] - (double)tJ[0];
-                F3y += (double)tA[1] - (double)tJ[1];
-                F3z += (double)tA[2] - (double)tJ[2];
+                d_e3<R>(mA.v, ux, uy, uz, g, hdg, hb, c0, tA, HA);
+                d_e3<R>(mJ.v, -ux, -uy, -uz, g, hdg, hb, c0, tJ, HJ);
+                F3x += (double)(tA[0] - tJ[0]);
+                F3y += (double)(tA[1] - tJ[1]);
+                F3z += (double)(tA[2] - tJ[2]);
                 vxx += (double)(tA[0] * ddx);
                 vyy += (double)(tA[1] * ddy);
                 vzz += (double)(tA[2] * ddz);
