@@ -34,7 +34,41 @@ C_MOM = 29      # g(r) and the 11 three-body moments per (centre, neighbour)
 C_D3 = 95       # three-body force/virial contribution per (centre, neighbour)
 C_ATOM2 = 50    # per atom in pass 2: own three-body energy, Einstein, kick, kinetic energy
 PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
+PEAK_HBM = 8.0e12                             # B/s
 SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
+
+# HBM bytes per launch of the force passes on this workload (64 replicas,
+# mixed precision, skin 1.4 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch, averaged over the dispatches of a short run), each
+# scaled by what the counter reads for a plain 512 MiB device copy: FETCH_SIZE
+# reads half the copied bytes (factor 2.000), WRITE_SIZE all of them (1.000).
+# The figures hold only for the kernel sources they were taken on (digest).
+MEASURED_TRAFFIC = {
+    "sources_sha256": "086e1941f4340d2a881261c051f611e2f79319a847247412ac7a4d952d0ec66c",
+    "skin": 1.4, "replicas": 64, "precision": "mixed",
+    "fetch_factor": 2.0, "write_factor": 1.0,
+    "kib": {"pass1": (32565.4, 45736.5), "pass2": (31094.0, 23321.8)},  # (FETCH_SIZE, WRITE_SIZE)
+}
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("swfe_kernels.hip", "swfe_internal.h"):
+        with open(os.path.join(ROOT, "paper_2103_10449_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name, skin, replicas, precision):
+    """HBM bytes per launch of kernel `name`, or None when the counters were
+    not taken on this configuration and these kernel sources."""
+    m = MEASURED_TRAFFIC
+    if (name not in m["kib"] or skin != m["skin"] or replicas != m["replicas"] or precision != m["precision"]
+            or kernel_sources_digest() != m["sources_sha256"]):
+        return None
+    fetch, write = m["kib"][name]
+    return 1024.0 * (fetch * m["fetch_factor"] + write * m["write_factor"])
 
 
 def kernel_flops(name, n_atoms, ordered_pairs):
@@ -110,20 +144,37 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
                 n_rep=len(specs))
 
 
-def cpu_baseline(wl_builder, P, seed, budget_s=12.0):
-    """The FP64 oracle on the same batch: full replica set, as many whole
-    steps as fit in about budget_s seconds (at least one)."""
+def _oracle_systems(specs):
     from oracle import oracle as orc
-    wl = wl_builder(10)
-    systems = []
-    wl.systems = copy.deepcopy(wl.systems)
-    for s in wl.systems:
-        systems.append(orc.OSystem(x=s.x, v=s.v, box=s.box, mode=s.mode, x0=s.x0, partner=s.partner,
-                                   k_spring=s.k_spring, T0=s.T0, tau_damp=s.tau_damp, p_damp=s.p_damp,
-                                   pressure=s.pressure, stream=s.stream, sched_start=s.sched_start,
-                                   sched_end=s.sched_end, sched_steps=s.sched_steps))
-    o = orc.Oracle(systems, P, dt=wl.dt, seed=seed)
-    n = sum(s.n for s in systems)
+    return [orc.OSystem(x=s.x, v=s.v, box=s.box, mode=s.mode, x0=s.x0, partner=s.partner,
+                        k_spring=s.k_spring, T0=s.T0, tau_damp=s.tau_damp, p_damp=s.p_damp,
+                        pressure=s.pressure, stream=s.stream, sched_start=s.sched_start,
+                        sched_end=s.sched_end, sched_steps=s.sched_steps) for s in specs]
+
+
+def _oracle_steps(job):
+    """Worker: the FP64 oracle on a share of the (independent) replicas for a
+    fixed number of steps; returns (atom-steps, seconds)."""
+    specs, P, dt, seed, n_steps = job
+    from oracle import oracle as orc
+    o = orc.Oracle(_oracle_systems(specs), P, dt=dt, seed=seed)
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        o.step()
+    return sum(s.n for s in specs) * n_steps, time.perf_counter() - t0
+
+
+def cpu_baseline(wl, P, seed, budget_s=12.0):
+    """The FP64 oracle on the same batch.  Single thread: every replica, as
+    many whole steps as fit in about budget_s (at least one).  All cores: the
+    replicas (independent systems) dealt to one process per core, each
+    stepping its share the same number of steps."""
+    import multiprocessing as mp
+    specs = copy.deepcopy(wl.systems)
+    n = sum(s.n for s in specs)
+    o_specs = _oracle_systems(specs)
+    from oracle import oracle as orc
+    o = orc.Oracle(o_specs, P, dt=wl.dt, seed=seed)
     t0 = time.perf_counter()
     k = 0
     while True:
@@ -131,10 +182,25 @@ def cpu_baseline(wl_builder, P, seed, budget_s=12.0):
         k += 1
         if time.perf_counter() - t0 > budget_s or k >= 10:
             break
-    dt = time.perf_counter() - t0
-    return dict(value=n * k / dt, unit="atom-steps/s", cores=1, kind="oracle",
-                sample=f"all {len(systems)} replicas ({n} atoms) of the batched workload, {k} steps, "
-                       f"{dt:.1f} s, single thread")
+    dt1 = time.perf_counter() - t0
+    single = n * k / dt1
+    cores = max(1, min(16, os.cpu_count() or 1, len(specs)))
+    # deal replicas largest first to the least loaded share
+    shares = [[] for _ in range(cores)]
+    load = [0] * cores
+    for s in sorted(specs, key=lambda s: -s.n):
+        q = load.index(min(load))
+        shares[q].append(s)
+        load[q] += s.n
+    jobs = [(sh, P, wl.dt, seed, k) for sh in shares if sh]
+    with mp.get_context("spawn").Pool(len(jobs)) as pool:
+        res = pool.map(_oracle_steps, jobs)
+    dtn = max(r[1] for r in res)  # the slowest share's stepping time
+    return dict(value=n * k / dtn, unit="atom-steps/s", cores=len(jobs), kind="oracle",
+                single_thread_value=single,
+                sample=f"all {len(specs)} replicas ({n} atoms) of the batched workload, {k} steps: "
+                       f"{len(jobs)} processes (replicas dealt by size), slowest share {dtn:.1f} s; "
+                       f"single thread {dt1:.1f} s")
 
 
 def main():
@@ -155,10 +221,9 @@ def main():
         print(f"bench.py runs on one GPU only: the batched replicas of this workload do not "
               f"communicate and are not split across GPUs (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
-    import torch
     from paper_2103_10449_amd import inputs
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calib_copy_mb:
+        import torch
         n = args.calib_copy_mb * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -173,6 +238,14 @@ def main():
     base = inputs.config4(n_rep=args.replicas, steps=steps // 2)
     print(f"# workload: {base.n_atoms} atoms in {len(base.systems)} replicas", file=sys.stderr, flush=True)
     builder = lambda half: base
+    # the oracle runs first, before this process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# oracle baseline on the host cores ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(base, P, seed)
+        print(f"# oracle: {cpu['value']:.3g} atom-steps/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     skins = (args.skin,) if args.skin > 0 else None
     mixed = run_precision("mixed", builder, steps, args.warmup, P, seed, args.profile_steps, skins)
@@ -221,9 +294,12 @@ def main():
         avg = prof[name] / n_prof / 1e3              # s per launch
         fl = kernel_flops(name, mixed["n_atoms"], mixed["pairs"])
         ach = fl / avg / 1e12 if fl else None
+        traffic = measured_traffic(name, mixed["skin"], args.replicas, "mixed")
         out["roofline"] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": PEAK["mixed"] / 1e12,
                            "unit": "TFLOP/s", "frac": (ach / (PEAK["mixed"] / 1e12)) if ach else None,
-                           "traffic": None, "avg_launch_us": 1e6 * avg,
+                           "traffic": traffic, "avg_launch_us": 1e6 * avg,
+                           "hbm_GBps": traffic / avg / 1e9 if traffic else None,
+                           "hbm_frac": traffic / avg / PEAK_HBM if traffic else None,
                            "per_kernel_us": {k: 1e3 * v / n_prof for k, v in prof.items()}}
         if fp64 is not None and fp64["prof"]:
             p64 = fp64["prof"]
@@ -232,8 +308,8 @@ def main():
             out["roofline_fp64"] = {"kernel": name, "achieved": fl64 / avg64 / 1e12, "peak": PEAK["fp64"] / 1e12,
                                     "frac": fl64 / avg64 / PEAK["fp64"],
                                     "per_kernel_us": {k: 1e3 * v / n_prof for k, v in p64.items()}}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(builder, P, seed)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
