@@ -72,6 +72,10 @@ typedef struct swfe_ctx swfe_ctx;
 #define SWFE_MODE_DCCI_T 6
 #define SWFE_MODE_DCCI_P 7
 
+/* Barostat kinds (swfe_system_desc.baro). */
+#define SWFE_BARO_ISO 0
+#define SWFE_BARO_ANISO 1
+
 /* precision of the pair and triplet term arithmetic */
 #define SWFE_PREC_FP64 0  /* everything FP64 */
 #define SWFE_PREC_MIXED 1 /* FP32 terms; FP64 positions, accumulation, work */
@@ -108,6 +112,11 @@ typedef struct {
      * DCCI_T: T in K.  sched_steps = 0 holds the start value. */
     double sched_start, sched_end;
     int64_t sched_steps;
+    /* barostat (p_damp > 0): SWFE_BARO_ISO, one piston for the volume; or
+     * SWFE_BARO_ANISO, one piston per box length (the paper's `aniso` runs of
+     * beta-tin, section 4.1), each of a third of the isotropic piston mass */
+    int32_t baro;
+    int32_t reserved;  /* set to 0 */
 } swfe_system_desc;
 
 /* Device buffers, all caller owned. */
@@ -132,13 +141,14 @@ typedef struct {
     double V;          /* volume, A^3 */
     double virial[9];  /* dU_int/dstrain (eV), row-major */
     double box[3];
-    double veps;       /* barostat rate (1/ps) */
+    double veps;       /* barostat rate d ln L / dt (1/ps); mean over the axes */
     double T_inst;     /* kinetic temperature over 3N-3 degrees of freedom */
     int64_t step;      /* steps taken since init (noise counter) */
     int64_t sched_k;   /* steps taken on the current schedule */
     int32_t err;       /* sticky device error bits of this system */
     int32_t pad;
     int64_t n_rebuild; /* Verlet-list rebuilds of this system so far */
+    double veps_axes[3]; /* per-axis barostat rates d ln L_a / dt (1/ps) */
 } swfe_system_state;
 
 /* Per-system row written by swfe_compute_forces when out != NULL. */

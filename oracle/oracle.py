@@ -16,7 +16,8 @@ Contents, each citing the passage of the paper it follows:
                    definition; drives the thermostat noise.
 * ``Oracle.step``  one step of the switched dynamics: the lambda switch with
                    its work increment (eq. Wdyn, section 2), velocity Verlet
-                   with a Langevin O-step and an isotropic barostat.
+                   with a Langevin O-step and an isotropic or per-axis
+                   (anisotropic) barostat.
 * schedules        Frenkel-Ladd lambda(t) (section 2.1), reversible scaling
                    lambda(t) = 1/(1 + t/t_s (1/lambda_f - 1)) with P_S =
                    lambda P (eqs. T_sc, P_sc, section 4.1), pressure switching
@@ -54,6 +55,9 @@ MASS_SI = 28.0855                                     # amu
 PARAM_NAMES = ("A", "B", "p", "q", "a", "lambda_sw", "gamma", "sigma", "epsilon")
 
 MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P = range(8)
+# barostat: one piston for the volume (isotropic) or one per box length (the
+# paper's `aniso` runs of beta-tin, section 4.1)
+BARO_ISO, BARO_ANISO = 0, 1
 ERR_DCCI_SINGULAR = 1
 
 
@@ -226,13 +230,15 @@ class OSystem:
     p_damp: float = 0.0
     pressure: float = 0.0          # GPa
     stream: int = 0
+    baro: int = BARO_ISO
     sched_start: float = 1.0
     sched_end: float = 1.0
     sched_steps: int = 0
     # dynamic state
     lam: float = 1.0
     Ps: float = 0.0                # scaled barostat target, eV/A^3
-    veps: float = 0.0              # barostat rate p_eps / W, 1/ps
+    veps: float = 0.0              # barostat rate p_eps / W, 1/ps (isotropic)
+    veps3: Optional[np.ndarray] = None  # per-axis rates d ln L_a / dt, 1/ps (anisotropic)
     W: float = 0.0                 # accumulated work, eV
     step: int = 0                  # global step counter (noise counter)
     k: int = 0                     # steps since the schedule started
@@ -254,6 +260,10 @@ class OSystem:
 
     def kinetic(self) -> float:
         return 0.5 * MASS_SI * MVV2E * float((self.v * self.v).sum())
+
+    def kinetic_axes(self) -> np.ndarray:
+        """K_a = m/2 sum_i v_ia^2 for a = x, y, z."""
+        return 0.5 * MASS_SI * MVV2E * (self.v * self.v).sum(axis=0)
 
     def temperature(self) -> float:
         return 2.0 * self.kinetic() / ((3 * self.n - 3) * KB)
@@ -349,7 +359,7 @@ class Oracle:
          W += H(lambda_{k+1}, z_k) - H(lambda_k, z_k)
       2. barostat half step of the piston rate
       3. B: half kick with F(lambda_{k+1})
-      4. A: half drift (with isotropic box scaling)
+      4. A: half drift (with box scaling, isotropic or per axis)
       5. O: Langevin step with zero-sum noise
       6. A: half drift
       7. interaction at the new positions
@@ -389,15 +399,51 @@ class Oracle:
         tr = float(np.trace(s.Xi_int))
         return lam * tr if s.mode in (MODE_RS, MODE_DCCI_T, MODE_DCCI_P) else tr
 
+    def _xi_diag(self, s: OSystem, lam: float) -> np.ndarray:
+        d = np.diag(s.Xi_int).copy()
+        return lam * d if s.mode in (MODE_RS, MODE_DCCI_T, MODE_DCCI_P) else d
+
     # ---- barostat -----------------------------------------------------------
     def _baro_half(self, s: OSystem, lam: float, Ps: float):
+        """Half step of the piston rate(s).  Isotropic (MTK, one piston of mass
+        W = (N_f + 3) kB T0 tau_p^2 for eps = ln L):
+            dv_eps/dt = [alpha 2K - tr Xi - 3 V P_S] / W,  alpha = 1 + 3/N_f.
+        Per axis (eps_a = ln L_a, pistons of mass W/3 so that equal stresses
+        move the three axes as the isotropic piston):
+            dv_a/dt = [2K_a + 2K/N_f - Xi_aa - V P_S] / (W/3)."""
         if s.p_damp <= 0.0:
             return
         nf = 3 * s.n - 3
-        alpha = 1.0 + 3.0 / nf
         wp = (nf + 3) * KB * s.T0 * s.p_damp ** 2
+        if s.baro == BARO_ANISO:
+            if s.veps3 is None:
+                s.veps3 = np.zeros(3)
+            g = 2.0 * s.kinetic_axes() + 2.0 * s.kinetic() / nf - self._xi_diag(s, lam) - s.volume * Ps
+            s.veps3 = s.veps3 + 0.5 * self.dt * g / (wp / 3.0)
+            return
+        alpha = 1.0 + 3.0 / nf
         g = alpha * 2.0 * s.kinetic() - self._xi_trace(s, lam) - 3.0 * s.volume * Ps
         s.veps += 0.5 * self.dt * g / wp
+
+    def _factors(self, s: OSystem):
+        """Per-axis factors of the kick (velocity damping by the piston:
+        dv_a/dt = F_a/m - (v_eps,a + tr v_eps / N_f) v_a) and of the drift
+        (dx_a/dt = v_a + v_eps,a x_a), exact over a half step."""
+        dt = self.dt
+        nf = 3 * s.n - 3
+        if s.baro == BARO_ANISO and s.p_damp > 0.0:
+            v3 = s.veps3 if s.veps3 is not None else np.zeros(3)
+            zk = (v3 + v3.sum() / nf) * 0.5 * dt
+            za = v3 * 0.5 * dt
+        else:
+            alpha = 1.0 + 3.0 / nf
+            zk = np.full(3, alpha * s.veps * 0.5 * dt)
+            za = np.full(3, s.veps * 0.5 * dt)
+        decay = np.exp(-zk)
+        phi = np.where(zk == 0.0, 1.0, -np.expm1(-zk) / np.where(zk == 0.0, 1.0, zk))
+        grow = np.exp(za)
+        psi = np.where(za == 0.0, 1.0, np.expm1(za) / np.where(za == 0.0, 1.0, za))
+        return decay, phi, grow, psi
 
     # ---- the step -----------------------------------------------------------
     def step(self):
@@ -433,14 +479,7 @@ class Oracle:
                 continue
             # 2. barostat half step
             self._baro_half(s, s.lam, s.Ps)
-            nf = 3 * s.n - 3
-            alpha = 1.0 + 3.0 / nf
-            zk = alpha * s.veps * 0.5 * dt
-            decay = np.exp(-zk)
-            phi = 1.0 if zk == 0.0 else -np.expm1(-zk) / zk
-            za = s.veps * 0.5 * dt
-            grow = np.exp(za)
-            psi = 1.0 if za == 0.0 else np.expm1(za) / za
+            decay, phi, grow, psi = self._factors(s)
             acc = 1.0 / MVV2E / MASS_SI
             # 3. B
             s.v = s.v * decay + 0.5 * dt * acc * self.total_force(s, s.lam) * phi

@@ -153,6 +153,8 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
             return fail(ctx, SWFE_E_INVALID_ARG, "a barostat (p_damp > 0) needs T0 > 0");
         if (q.mode == SWFE_MODE_FL && q.p_damp > 0)
             return fail(ctx, SWFE_E_INVALID_ARG, "Frenkel-Ladd switching runs at fixed volume");
+        if (q.baro != SWFE_BARO_ISO && q.baro != SWFE_BARO_ANISO)
+            return fail(ctx, SWFE_E_INVALID_ARG, "baro must be SWFE_BARO_ISO or SWFE_BARO_ANISO");
         if (q.mode == SWFE_MODE_RS && !(q.sched_start > 0 && q.sched_end > 0))
             return fail(ctx, SWFE_E_INVALID_ARG, "reversible scaling needs lambda > 0");
         if (q.mode == SWFE_MODE_DCCI_T && !(q.sched_start > 0 && q.sched_end > 0 && q.T0 > 0))
@@ -172,6 +174,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         sd.n = q.n_atoms;
         sd.mode = q.mode;
         sd.partner = is_dcci(q.mode) ? q.partner : -1;
+        sd.baro = q.baro;
         // Cell capacity for boxes up to 1.3x the initial length; cells are at
         // least rc + skin >= rc, so rc bounds the count for every skin.
         int64_t cap = 1;
@@ -527,7 +530,7 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
             x.box_build[k] = d[i].box[k];
             x.pscale[k] = 1.0;
         }
-        x.decay = x.phi = x.grow = x.psi = 1.0;
+        for (int k = 0; k < 3; ++k) x.decay[k] = x.phi[k] = x.grow[k] = x.psi[k] = 1.0;
     }
     HIPCHK(ctx, hipMemcpyAsync(q.state, st.data(), sizeof(SysState) * n_sys, hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipMemsetAsync(q.cell_count, 0, 4 * (size_t)ctx->plan.cells, s));
@@ -685,7 +688,8 @@ int swfe_get_state(swfe_ctx *ctx, swfe_system_state *out, void *stream)
         o.V = x.box[0] * x.box[1] * x.box[2];
         for (int k = 0; k < 9; ++k) o.virial[k] = x.vir[k];
         for (int k = 0; k < 3; ++k) o.box[k] = x.box[k];
-        o.veps = x.veps;
+        o.veps = (x.veps[0] + x.veps[1] + x.veps[2]) / 3.0;
+        for (int k = 0; k < 3; ++k) o.veps_axes[k] = x.veps[k];
         o.T_inst = 2.0 * x.K / (d.nf * kKB);
         o.step = x.step;
         o.sched_k = x.k;

@@ -20,10 +20,10 @@ enum : int {
     P_VIR = 1,      // 9 virial components dE/dstrain
     P_DTH = 10,     // 9 parameter derivatives
     P_UREF = 19,    // pass 2: Einstein energy
-    P_K = 20,       // pass 2: kinetic energy
-    P_NOISE = 21,   // pass 2: 3 sums of the next O step's normals
+    P_K = 20,       // pass 2: kinetic energy per axis (3)
+    P_NOISE = 23,   // pass 2: 3 sums of the next O step's normals
     P_E3 = 19,      // pass 1: three-body energy (slot 19 of the pass-1 row)
-    kNumPart = 24
+    kNumPart = 26
 };
 
 // Device error bits (per system, sticky until read by the host).
@@ -48,6 +48,7 @@ struct SysDesc {
     int32_t nc_max[3];
     int32_t tile_begin, tile_end; // tiles of this system (contiguous)
     int32_t group;                // reduction group (a system or a dCCI pair)
+    int32_t baro;                 // 0: one piston (volume), 1: one piston per axis
     double k_spring, T0, tau_damp, p_damp;
     double pressure;          // eV/A^3
     double nf;                // 3N - 3
@@ -70,14 +71,16 @@ struct Group {
 
 // Dynamic per-system state (device resident).
 struct SysState {
-    double lam, Ps, W, veps;
+    double lam, Ps, W;
+    double veps[3];                 // piston rates d ln L_a / dt (equal when isotropic)
     double box[3];
     double box_build[3];            // box in which the Verlet list was built
     double U_int, U_ref, K, V, E2, E3;
+    double K3[3];                   // kinetic energy per axis
     double vir[9];
     double dth[9];
     double noise_mean[3];
-    double decay, phi, grow, psi;   // integrator factors of the current step
+    double decay[3], phi[3], grow[3], psi[3];  // per-axis integrator factors of the current step
     double pscale[3];               // diagonal strain applied by compute_forces
     int64_t step;                   // steps since set-up (noise counter)
     int64_t k;                      // steps on the current schedule

@@ -352,12 +352,12 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
             const double4 f = p.fs[t];
             const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
             const double hdt = 0.5 * c.dt, ka = hdt * d.acc;
-            v.x = v.x * st.decay + ka * total_force(d.mode, st.lam, f.x, x.x, x0.x, d.k_spring) * st.phi;
-            v.y = v.y * st.decay + ka * total_force(d.mode, st.lam, f.y, x.y, x0.y, d.k_spring) * st.phi;
-            v.z = v.z * st.decay + ka * total_force(d.mode, st.lam, f.z, x.z, x0.z, d.k_spring) * st.phi;
-            x.x = x.x * st.grow + (v.x * hdt) * st.psi;
-            x.y = x.y * st.grow + (v.y * hdt) * st.psi;
-            x.z = x.z * st.grow + (v.z * hdt) * st.psi;
+            v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, f.x, x.x, x0.x, d.k_spring) * st.phi[0];
+            v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, f.y, x.y, x0.y, d.k_spring) * st.phi[1];
+            v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, f.z, x.z, x0.z, d.k_spring) * st.phi[2];
+            x.x = x.x * st.grow[0] + (v.x * hdt) * st.psi[0];
+            x.y = x.y * st.grow[1] + (v.y * hdt) * st.psi[1];
+            x.z = x.z * st.grow[2] + (v.z * hdt) * st.psi[2];
             if (o_step_on(d)) {
                 // this step's normals, drawn by the force pass that ended
                 // the previous step (it also formed their mean)
@@ -367,9 +367,9 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
                 v.y = d.c1 * v.y + c2s * (z.y - st.noise_mean[1]);
                 v.z = d.c1 * v.z + c2s * (z.z - st.noise_mean[2]);
             }
-            x.x = x.x * st.grow + (v.x * hdt) * st.psi;
-            x.y = x.y * st.grow + (v.y * hdt) * st.psi;
-            x.z = x.z * st.grow + (v.z * hdt) * st.psi;
+            x.x = x.x * st.grow[0] + (v.x * hdt) * st.psi[0];
+            x.y = x.y * st.grow[1] + (v.y * hdt) * st.psi[1];
+            x.z = x.z * st.grow[2] + (v.z * hdt) * st.psi[2];
             p.xs[t] = x;
             p.vs[t] = v;
             double box[3], ibox[3];
@@ -904,13 +904,28 @@ __device__ double h_switch(const SysDesc &d, const SysState &st, double lam, dou
     }
 }
 
+// Barostat half step (MTK).  One piston of mass W for eps = ln L:
+//   dv/dt = [alpha 2K - tr Xi - 3 V P_S] / W,  alpha = 1 + 3/N_f;
+// or one piston per axis (eps_a = ln L_a), of mass W/3 so that equal axis
+// stresses move the three axes as the single piston:
+//   dv_a/dt = [2K_a + 2K/N_f - Xi_aa - V P_S] / (W/3).
 __device__ void baro_half(const SysDesc &d, SysState &st, double dt)
 {
     if (d.p_damp <= 0.0 || d.mode == MODE_FORCE) return;
+    const double ls = scales_interaction(d.mode) ? st.lam : 1.0;
+    if (d.baro) {
+        for (int a = 0; a < 3; ++a) {
+            const double xi = ls * st.vir[4 * a];
+            const double g = 2.0 * st.K3[a] + 2.0 * st.K / d.nf - xi - st.V * st.Ps;
+            st.veps[a] += 0.5 * dt * g / (d.wpiston / 3.0);
+        }
+        return;
+    }
     double tr = st.vir[0] + st.vir[4] + st.vir[8];
     if (scales_interaction(d.mode)) tr = st.lam * tr;
     const double g = d.alpha * 2.0 * st.K - tr - 3.0 * st.V * st.Ps;
-    st.veps += 0.5 * dt * g / d.wpiston;
+    const double v = st.veps[0] + 0.5 * dt * g / d.wpiston;
+    st.veps[0] = st.veps[1] = st.veps[2] = v;
 }
 
 // dCCI coupling (section 3): next (lambda, P_S) of a pair from instantaneous
@@ -972,14 +987,19 @@ __device__ void apply_switch(const SysDesc &d, SysState &st, double lam, double 
 // integrator factors for the coming step; moves the box to its post-drift size
 __device__ void step_factors(const SysDesc &d, SysState &st, double dt, double rc)
 {
-    const double zk = d.alpha * st.veps * 0.5 * dt;
-    st.decay = exp(-zk);
-    st.phi = zk == 0.0 ? 1.0 : -expm1(-zk) / zk;
-    const double za = st.veps * 0.5 * dt;
-    st.grow = exp(za);
-    st.psi = za == 0.0 ? 1.0 : expm1(za) / za;
+    // velocities: dv_a/dt = F_a/m - (v_eps,a + tr v_eps / N_f) v_a; positions:
+    // dx_a/dt = v_a + v_eps,a x_a; both exact over a half step
+    const double tr = st.veps[0] + st.veps[1] + st.veps[2];
+    for (int a = 0; a < 3; ++a) {
+        const double zk = d.baro ? (st.veps[a] + tr / d.nf) * 0.5 * dt : d.alpha * st.veps[a] * 0.5 * dt;
+        st.decay[a] = exp(-zk);
+        st.phi[a] = zk == 0.0 ? 1.0 : -expm1(-zk) / zk;
+        const double za = st.veps[a] * 0.5 * dt;
+        st.grow[a] = exp(za);
+        st.psi[a] = za == 0.0 ? 1.0 : expm1(za) / za;
+    }
     if (d.mode != MODE_FORCE)
-        for (int k = 0; k < 3; ++k) st.box[k] = (st.box[k] * st.grow) * st.grow;
+        for (int k = 0; k < 3; ++k) st.box[k] = (st.box[k] * st.grow[k]) * st.grow[k];
     for (int k = 0; k < 3; ++k)
         if (!(st.box[k] >= 2.0 * rc)) st.err |= ERR_BOX;
 }
@@ -1055,7 +1075,8 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
         for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
         for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
         st.U_ref = b[P_UREF];
-        st.K = b[P_K];
+        for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
+        st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
         for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
         st.V = st.box[0] * st.box[1] * st.box[2];
         if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
@@ -1096,7 +1117,7 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
 template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass2(Ctl c, DevPtrs p, SwParams sw)
 {
-    constexpr int NV = 24;  // -, virial 9, dtheta 9, U_ref, K, noise 3
+    constexpr int NV = kNumPart;  // -, virial 9, dtheta 9, U_ref, K per axis 3, noise 3
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -1206,21 +1227,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         double4 v = v0;
         if (c.in_step && d.mode != MODE_FORCE) {
             const double ka = (0.5 * c.dt) * d.acc;
-            v.x = v.x * st.decay + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring) * st.phi;
-            v.y = v.y * st.decay + ka * total_force(d.mode, st.lam, F.y, xa.y, x0.y, d.k_spring) * st.phi;
-            v.z = v.z * st.decay + ka * total_force(d.mode, st.lam, F.z, xa.z, x0.z, d.k_spring) * st.phi;
+            v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring) * st.phi[0];
+            v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, F.y, xa.y, x0.y, d.k_spring) * st.phi[1];
+            v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, F.z, xa.z, x0.z, d.k_spring) * st.phi[2];
             p.vs[t] = v;
         }
-        acc[20] = d.mvv2e_m * (v.x * v.x + v.y * v.y + v.z * v.z);
+        acc[P_K] = d.mvv2e_m * (v.x * v.x);
+        acc[P_K + 1] = d.mvv2e_m * (v.y * v.y);
+        acc[P_K + 2] = d.mvv2e_m * (v.z * v.z);
         // normals of the next O step: stored for it, and summed for its
         // zero-sum correction
         if (o_step_on(d)) {
             double z[3];
             normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)atom, z);
             p.zs[t] = make_double4(z[0], z[1], z[2], 0.0);
-            acc[21] = z[0];
-            acc[22] = z[1];
-            acc[23] = z[2];
+            acc[P_NOISE] = z[0];
+            acc[P_NOISE + 1] = z[1];
+            acc[P_NOISE + 2] = z[2];
         }
     }
     block_reduce<NV>(acc, p.part2 + (int64_t)ti * kNumPart);

@@ -177,6 +177,7 @@ def maxwell(n_atoms: int, T: float, g: np.random.Generator,
 # 5 pressure switching, 6 dCCI (temperature control), 7 dCCI (pressure control)
 # ----------------------------------------------------------------------------
 MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P = range(8)
+BARO_ISO, BARO_ANISO = 0, 1
 
 
 @dataclass
@@ -194,6 +195,7 @@ class SystemSpec:
     p_damp: float = 0.0            # barostat period, ps (0: fixed box)
     pressure: float = 0.0          # physical pressure P, GPa
     stream: int = 0                # noise stream id (Philox key word 1)
+    baro: int = 0                  # 0: one piston (volume), 1: one piston per box length
     # schedule: lam_start/lam_end (FL, RS), or the controlled variable's
     # start/end (P in GPa for pressure switching and dCCI-P, T in K for dCCI-T)
     sched_start: float = 1.0

@@ -20,6 +20,7 @@ OK = 0
 E_INVALID_ARG, E_BOX_TOO_SMALL, E_OVERFLOW, E_NONFINITE, E_DCCI_SINGULAR, E_HIP, E_STATE, E_NOMEM = \
     -1, -2, -3, -4, -5, -6, -7, -8
 MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P = range(8)
+BARO_ISO, BARO_ANISO = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 PARAM_GRAD, STRAIN = 1, 2
 OUT_STRIDE = 20
@@ -44,7 +45,7 @@ class SystemDesc(ctypes.Structure):
                 ("k_spring", ctypes.c_double), ("T0", ctypes.c_double), ("tau_damp", ctypes.c_double),
                 ("p_damp", ctypes.c_double), ("pressure", ctypes.c_double), ("stream", ctypes.c_uint64),
                 ("sched_start", ctypes.c_double), ("sched_end", ctypes.c_double),
-                ("sched_steps", ctypes.c_int64)]
+                ("sched_steps", ctypes.c_int64), ("baro", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Buffers(ctypes.Structure):
@@ -59,7 +60,7 @@ class SystemState(ctypes.Structure):
                 ("V", ctypes.c_double), ("virial", ctypes.c_double * 9), ("box", ctypes.c_double * 3),
                 ("veps", ctypes.c_double), ("T_inst", ctypes.c_double), ("step", ctypes.c_int64),
                 ("sched_k", ctypes.c_int64), ("err", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("n_rebuild", ctypes.c_int64)]
+                ("n_rebuild", ctypes.c_int64), ("veps_axes", ctypes.c_double * 3)]
 
 
 EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_bytes", "swfe_init_system",
@@ -145,6 +146,8 @@ def system_descs(systems: Sequence) -> "ctypes.Array":
         d.sched_start = float(getattr(s, "sched_start", 1.0))
         d.sched_end = float(getattr(s, "sched_end", 1.0))
         d.sched_steps = int(getattr(s, "sched_steps", 0))
+        d.baro = int(getattr(s, "baro", 0))
+        d.reserved = 0
         off += d.n_atoms
     return arr
 
@@ -276,8 +279,8 @@ class Engine:
         for s in arr:
             out.append(dict(lam=s.lam, Ps=s.Ps, W=s.W, U_int=s.U_int, U_ref=s.U_ref, K=s.K, V=s.V,
                             virial=np.array(s.virial[:]).reshape(3, 3), box=np.array(s.box[:]),
-                            veps=s.veps, T=s.T_inst, step=s.step, sched_k=s.sched_k, err=s.err,
-                            n_rebuild=s.n_rebuild))
+                            veps=s.veps, veps_axes=np.array(s.veps_axes[:]), T=s.T_inst, step=s.step,
+                            sched_k=s.sched_k, err=s.err, n_rebuild=s.n_rebuild))
         return out
 
     def set_log(self, every: int, capacity: int = 4096):

@@ -79,3 +79,32 @@ def test_calls_before_init_fail_cleanly(swfe):
     assert lib.swfe_step_switched(ctx, 10, 1, None) == swfe.E_STATE
     assert b"not initialised" in lib.swfe_last_error(ctx)
     lib.swfe_destroy(ctx)
+
+
+def test_header_structs_match_binding(tmp_path):
+    """Sizes and field offsets of the C structs in include/swfe.h, compiled
+    with the host compiler, equal those of the ctypes mirrors."""
+    import ctypes
+    import subprocess
+    from paper_2103_10449_amd import swfe as m
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"swfe_system_desc": m.SystemDesc, "swfe_system_state": m.SystemState,
+               "swfe_buffers": m.Buffers, "swfe_sw_params": m.SwParams}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "swfe.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
