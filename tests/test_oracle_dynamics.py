@@ -133,6 +133,37 @@ def test_ideal_gas_npt_volume(sw_params):
     assert np.mean(Vs) == pytest.approx(Vexp, rel=0.05)
 
 
+def test_pressure_switching_ideal_gas_gibbs_closed_form(sw_params):
+    """Pressure switching (eq. Wmech_dyn) of an ideal gas (SW off) from 0.1
+    to 0.2 GPa and back: 1/2 (W_fwd - W_bwd) estimates G(P1) - G(P0) =
+    (N_pos + 1) kB T ln(P1/P0) with N_pos = N - 1 (centre of mass frozen in
+    scaled coordinates), 0.478 eV for N = 8 at 1000 K; (N_pos + 2) would be
+    12 % higher."""
+    P = dict(sw_params)
+    P["epsilon"] = 0.0
+    N, T = 8, 1000.0
+    P0, P1, n = 0.1, 0.2, 10000
+    L = (N * orc.KB * T / (P0 / orc.GPA_PER_EV_A3)) ** (1 / 3)
+    g = inputs.rng(961, 0, 0)
+    s = orc.OSystem(x=g.random((N, 3)) * L, v=inputs.maxwell(N, T, inputs.rng(961, 0, 1)),
+                    box=np.array([L, L, L]), mode=orc.MODE_AS_P, T0=T, tau_damp=0.05, p_damp=0.1,
+                    stream=4, sched_start=P0, sched_end=P0, sched_steps=0)
+    o = orc.Oracle([s], P, seed=6)
+    o.run(3000)                                    # equilibrate at P0
+    dG = []
+    for rep in range(2):
+        s.sched_start, s.sched_end, s.sched_steps = P0, P1, n
+        orc.initial_switch_state(s)
+        o.run(n)
+        wf = s.W
+        s.sched_start, s.sched_end = P1, P0
+        orc.initial_switch_state(s)
+        o.run(n)
+        dG.append(0.5 * (wf - s.W))
+    expect = N * orc.KB * T * np.log(P1 / P0)
+    assert np.mean(dG) == pytest.approx(expect, rel=0.06)
+
+
 @pytest.mark.parametrize("baro", [orc.BARO_ISO, orc.BARO_ANISO])
 def test_barostat_conserves_extended_energy(sw_params, baro):
     """Without the thermostat the barostat equations conserve
