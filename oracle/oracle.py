@@ -12,6 +12,9 @@ Contents, each citing the passage of the paper it follows:
                    silicon model (applications section).
 * ``einstein``     Einstein-crystal reference (section 2.1, the reference
                    system for solids).
+* ``uf_eval``      Uhlenbeck-Ford fluid reference (section 4.1, p = 25,
+                   sigma = 2.0; model of Leite et al.), switched to like the
+                   Einstein crystal: H = lam U + (1 - lam) U_UF.
 * ``philox4x64``   Philox4x64-10 (Salmon et al., SC'11), from its published
                    definition; drives the thermostat noise.
 * ``Oracle.step``  one step of the switched dynamics: the lambda switch with
@@ -55,6 +58,8 @@ MASS_SI = 28.0855                                     # amu
 PARAM_NAMES = ("A", "B", "p", "q", "a", "lambda_sw", "gamma", "sigma", "epsilon")
 
 MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P = range(8)
+# switching between the interaction and the Uhlenbeck-Ford fluid (section 4.1)
+MODE_UF = 8
 # barostat: one piston for the volume (isotropic) or one per box length (the
 # paper's `aniso` runs of beta-tin, section 4.1)
 BARO_ISO, BARO_ANISO = 0, 1
@@ -89,6 +94,9 @@ def _load():
                                     dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_sw_eval.restype = ctypes.c_int
         lib.orc_einstein.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp]
+        lib.orc_uf_eval.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, dp, dp, dp, dp]
+        lib.orc_uf_eval.restype = ctypes.c_int
         lib.orc_einstein.restype = ctypes.c_double
         _lib = lib
     return _lib
@@ -139,6 +147,26 @@ def sw_eval(x: np.ndarray, box, params: dict, force_images: bool = False,
         raise MemoryError("oracle neighbour list allocation failed")
     return dict(E2=e[0], E3=e[1], E=e[0] + e[1], F=F, virial=vir.reshape(3, 3),
                 dtheta=dth, e_atom=ea, nnb=nnb)
+
+
+def uf_eval(x: np.ndarray, box, p: float, sigma: float, T: float, rcut: float,
+            force_images: bool = False) -> dict:
+    """Uhlenbeck-Ford reference (section 4.1; Leite et al.): energy, forces,
+    virial and per-atom energy of phi(r) = -p kB T ln(1 - exp(-(r/sigma)^2)),
+    truncated at rcut."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[0]
+    h = cell_matrix(box)
+    e = np.zeros(1)
+    F = np.zeros((n, 3))
+    vir = np.zeros(9)
+    ea = np.zeros(n)
+    rc = lib.orc_uf_eval(n, _ptr(x), _ptr(h), p * KB * T, sigma, rcut, int(force_images), _ptr(e), _ptr(F),
+                         _ptr(vir), _ptr(ea))
+    if rc != 0:
+        raise MemoryError("oracle neighbour list allocation failed")
+    return dict(E=e[0], F=F, virial=vir.reshape(3, 3), e_atom=ea)
 
 
 def einstein(x: np.ndarray, x0: np.ndarray, k: float):
@@ -231,6 +259,11 @@ class OSystem:
     pressure: float = 0.0          # GPa
     stream: int = 0
     baro: int = BARO_ISO
+    # Uhlenbeck-Ford reference (MODE_UF): p, sigma (A), temperature (K), cutoff (A)
+    uf_p: float = 25.0
+    uf_sigma: float = 2.0
+    uf_T: float = 0.0
+    uf_rcut: float = 8.0
     sched_start: float = 1.0
     sched_end: float = 1.0
     sched_steps: int = 0
@@ -284,7 +317,7 @@ def _controlled(s: OSystem, k: int) -> float:
 
 def initial_switch_state(s: OSystem):
     """lambda and P_S at the start of a schedule."""
-    if s.mode == MODE_FL:
+    if s.mode in (MODE_FL, MODE_UF):
         s.lam, s.Ps = s.sched_start, 0.0
     elif s.mode == MODE_RS:
         # reversible scaling: T = T0/lambda (eq. T_sc), P_S = lambda P (eq. P_sc)
@@ -313,7 +346,7 @@ def _lam_rs(s: OSystem, k: int) -> float:
 
 def hamiltonian_switch_part(s: OSystem, lam: float, Ps: float) -> float:
     """The lambda- and P_S-dependent part of H at the current microstate."""
-    if s.mode == MODE_FL:
+    if s.mode in (MODE_FL, MODE_UF):
         return lam * s.U_int + (1.0 - lam) * s.U_ref
     if s.mode in (MODE_RS, MODE_DCCI_T, MODE_DCCI_P):
         return lam * s.U_int + Ps * s.volume
@@ -385,11 +418,14 @@ class Oracle:
         s.F_int, s.U_int, s.Xi_int = r["F"], r["E"], r["virial"]
         if s.mode == MODE_FL and s.x0 is not None:
             s.U_ref, s.F_ref = einstein(s.x, s.x0, s.k_spring)
+        elif s.mode == MODE_UF:
+            u = uf_eval(s.x, s.box, s.uf_p, s.uf_sigma, s.uf_T, s.uf_rcut)
+            s.U_ref, s.F_ref = u["E"], u["F"]
         else:
             s.U_ref, s.F_ref = 0.0, np.zeros_like(s.x)
 
     def total_force(self, s: OSystem, lam: float) -> np.ndarray:
-        if s.mode == MODE_FL:
+        if s.mode in (MODE_FL, MODE_UF):
             return lam * s.F_int + (1.0 - lam) * s.F_ref
         if s.mode in (MODE_RS, MODE_DCCI_T, MODE_DCCI_P):
             return lam * s.F_int
@@ -456,7 +492,7 @@ class Oracle:
                     new.append((lam, Ps, bad))
                 else:
                     new.append(None)
-            elif s.mode == MODE_FL:
+            elif s.mode in (MODE_FL, MODE_UF):
                 new.append((_controlled(s, s.k + 1), 0.0, False))
             elif s.mode == MODE_RS:
                 lam = _lam_rs(s, s.k + 1)

@@ -248,6 +248,47 @@ double orc_einstein(int n, const double* x, const double* x0, double k, double* 
     return U;
 }
 
+/*
+ * Uhlenbeck-Ford pair potential, the fluid reference the paper switches its
+ * liquids to (section 4.1, model of Leite et al., p = 25, sigma = 2.0 A):
+ *   phi_UF(r) = -p kB T_UF ln(1 - exp(-(r/sigma)^2))   r < rcut, 0 beyond
+ * pkT = p kB T_UF in eV.  Every ordered pair carries half of phi, as in
+ * orc_sw_eval; forces are -dE/dr, the virial dE/d(strain).
+ */
+int orc_uf_eval(int n, const double* x, const double* h, double pkT, double sigma, double rcut,
+                int force_images, double* out_e, double* f, double* vir, double* e_atom)
+{
+    int* start;
+    orc_nb_t* nb;
+    if (neighbours(n, x, h, rcut, force_images, &start, &nb)) return -1;
+    double E = 0.0, X[9] = {0};
+    if (f) memset(f, 0, sizeof(double) * 3 * n);
+    if (e_atom) memset(e_atom, 0, sizeof(double) * n);
+    const double is2 = 1.0 / (sigma * sigma);
+    for (int i = 0; i < n; ++i) {
+        for (int e = start[i]; e < start[i + 1]; ++e) {
+            const orc_nb_t* b = &nb[e];
+            double r = b->r, u = r * r * is2;
+            double om = -expm1(-u);                        /* 1 - exp(-u) */
+            double phi = -pkT * log(om);
+            double dphi = -pkT * (2.0 * r * is2) * exp(-u) / om;   /* dphi/dr */
+            E += 0.5 * phi;
+            if (e_atom) e_atom[i] += 0.5 * phi;
+            double gvec[3];
+            for (int a = 0; a < 3; ++a) gvec[a] = 0.5 * dphi * b->d[a] / r;
+            if (f)
+                for (int a = 0; a < 3; ++a) { f[3 * b->j + a] -= gvec[a]; f[3 * i + a] += gvec[a]; }
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) X[a * 3 + c] += gvec[a] * b->d[c];
+        }
+    }
+    *out_e = E;
+    if (vir) memcpy(vir, X, sizeof X);
+    free(start);
+    free(nb);
+    return 0;
+}
+
 /* Total neighbour-pair count (ordered) for a system, for workload statistics. */
 int orc_count_neighbours(int n, const double* x, const double* h, double rc, int64_t* total)
 {

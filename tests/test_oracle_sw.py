@@ -197,3 +197,66 @@ def test_einstein_reference():
     xm[2, 1] -= h
     fd = -(orc.einstein(xp, x0, 3.0)[0] - orc.einstein(xm, x0, 3.0)[0]) / (2 * h)
     assert fd == pytest.approx(F[2, 1], rel=1e-8)
+
+
+# ------------------------------------------------ Uhlenbeck-Ford reference ----
+UF = dict(p=25.0, sigma=2.0, T=2200.0)
+
+
+def test_uf_second_virial_coefficient_closed_form():
+    """The oracle's UF pair energy, through its Mayer function
+    f(r) = exp(-phi(r)/kB T) - 1 = (1 - exp(-(r/s)^2))^p - 1 at the model's
+    own temperature, integrates to the closed form
+    B2 = -2 pi int f r^2 dr = (pi^(3/2) s^3 / 2) sum_k (-1)^(k+1) C(p,k) k^(-3/2)
+    (binomial expansion and Gaussian integrals); 129.86 A^3 for p = 25,
+    s = 2 A.  A wrong exponent, p, sigma or temperature scaling fails this."""
+    from math import comb, fsum, pi
+    from scipy.integrate import quad
+    p, s, T = UF["p"], UF["sigma"], UF["T"]
+    rcut = 12 * s
+    box = np.array([4 * rcut] * 3)
+
+    def f(r):
+        x = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+        e = orc.uf_eval(x, box, p, s, T, rcut)["E"]
+        return (np.exp(-e / (orc.KB * T)) - 1.0) * r * r
+
+    integral = quad(f, 1e-6, rcut, limit=200, epsabs=1e-12, epsrel=1e-11)[0]
+    B2 = -2 * pi * integral
+    closed = pi ** 1.5 * s ** 3 / 2 * fsum((-1) ** (k + 1) * comb(int(p), k) * k ** -1.5 for k in range(1, int(p) + 1))
+    assert closed == pytest.approx(129.861039, rel=1e-6)
+    assert B2 == pytest.approx(closed, rel=1e-8)
+
+
+def test_uf_forces_and_virial_finite_difference():
+    x, box = inputs.liquid_rsa(64, inputs.rng(904, 0, 0))
+    r = orc.uf_eval(x, box, UF["p"], UF["sigma"], UF["T"], 8.0)
+    fs = max(np.abs(r["F"]).max(), 1.0)
+    assert np.abs(r["F"].sum(axis=0)).max() < 1e-11 * fs * len(x)
+    h = 1e-5
+    g = inputs.rng(904, 0, 1)
+    for i in g.choice(len(x), 6, replace=False):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            fd = -(orc.uf_eval(xp, box, UF["p"], UF["sigma"], UF["T"], 8.0)["E"]
+                   - orc.uf_eval(xm, box, UF["p"], UF["sigma"], UF["T"], 8.0)["E"]) / (2 * h)
+            assert abs(fd - r["F"][i, a]) < 1e-7 * fs
+    H0 = np.diag(box)
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = h
+            Ep = orc.uf_eval(x @ (np.eye(3) + e).T, (np.eye(3) + e) @ H0, UF["p"], UF["sigma"], UF["T"], 8.0)["E"]
+            Em = orc.uf_eval(x @ (np.eye(3) - e).T, (np.eye(3) - e) @ H0, UF["p"], UF["sigma"], UF["T"], 8.0)["E"]
+            assert (Ep - Em) / (2 * h) == pytest.approx(r["virial"][a, b], abs=1e-6 * max(1.0, np.abs(r["virial"]).max()))
+
+
+def test_uf_minimum_image_equals_explicit_images():
+    x, box = inputs.liquid_rsa(512, inputs.rng(904, 1, 0))
+    assert box.min() > 2 * 7.0
+    a = orc.uf_eval(x, box, UF["p"], UF["sigma"], UF["T"], 7.0)
+    b = orc.uf_eval(x, box, UF["p"], UF["sigma"], UF["T"], 7.0, force_images=True)
+    assert a["E"] == pytest.approx(b["E"], rel=1e-13)
+    assert np.allclose(a["F"], b["F"], atol=1e-12)
