@@ -149,7 +149,8 @@ def _oracle_systems(specs):
     return [orc.OSystem(x=s.x, v=s.v, box=s.box, mode=s.mode, x0=s.x0, partner=s.partner,
                         k_spring=s.k_spring, T0=s.T0, tau_damp=s.tau_damp, p_damp=s.p_damp,
                         pressure=s.pressure, stream=s.stream, sched_start=s.sched_start,
-                        sched_end=s.sched_end, sched_steps=s.sched_steps, baro=s.baro) for s in specs]
+                        sched_end=s.sched_end, sched_steps=s.sched_steps, baro=s.baro, uf_p=s.uf_p, uf_sigma=s.uf_sigma,
+                        uf_T=s.uf_T, uf_rcut=s.uf_rcut) for s in specs]
 
 
 def _oracle_steps(job):

@@ -62,6 +62,9 @@ typedef struct swfe_ctx swfe_ctx;
  * AS_P    pressure switching, work = int dP/dt V dt (eq. Wmech_dyn)
  * DCCI_T  dCCI with lambda (temperature) control (eq. Ps_coex_discreted)
  * DCCI_P  dCCI with pressure control (eq. l_coex_discreted)
+ * UF      H = lam H_int + (1-lam) U_UF with the Uhlenbeck-Ford fluid as the
+ *         reference of a liquid (section 4.1), lambda linear in time; fixed
+ *         volume.  The work and U_ref are as for FL, with U_ref = U_UF.
  */
 #define SWFE_MODE_FORCE 0
 #define SWFE_MODE_NVE 1
@@ -71,6 +74,7 @@ typedef struct swfe_ctx swfe_ctx;
 #define SWFE_MODE_AS_P 5
 #define SWFE_MODE_DCCI_T 6
 #define SWFE_MODE_DCCI_P 7
+#define SWFE_MODE_UF 8
 
 /* Barostat kinds (swfe_system_desc.baro). */
 #define SWFE_BARO_ISO 0
@@ -117,6 +121,11 @@ typedef struct {
      * beta-tin, section 4.1), each of a third of the isotropic piston mass */
     int32_t baro;
     int32_t reserved;  /* set to 0 */
+    /* Uhlenbeck-Ford fluid reference (SWFE_MODE_UF, section 4.1; model of
+     * Leite et al.): phi(r) = -p kB T_UF ln(1 - exp(-(r/sigma)^2)) for
+     * r < rcut.  UF systems run at fixed volume (p_damp = 0); each box length
+     * must be at least 2 rcut.  Ignored by the other modes. */
+    double uf_p, uf_sigma, uf_T, uf_rcut;
 } swfe_system_desc;
 
 /* Device buffers, all caller owned. */

@@ -29,7 +29,7 @@ constexpr double kDefaultSkin = 0.5;                                    // A
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s, zs, xf;
+    size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s, zs, xf, fref;
     size_t perm, tperm, norder, rank, cellid, nnb, sl, cell_count, cell_start, nl, nl_cnt, mom, e_s;
     size_t part1, part2, disp_max, work, n_work, desc, state, tiles, groups, log, strain, total;
 };
@@ -40,6 +40,7 @@ struct Plan {
     int64_t n_total = 0;
     int64_t cells = 0;       // sum of per-system cell capacities
     int64_t max_tiles = 0;   // tiles at the smallest block size
+    int32_t list_cap = kMaxList;  // Verlet-list rows per atom
     Layout lay{};
 };
 
@@ -140,13 +141,18 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
                      (long long)off);
             return fail(ctx, SWFE_E_INVALID_ARG, msg);
         }
+        if (q.mode < 0 || q.mode > 8) return fail(ctx, SWFE_E_INVALID_ARG, "unknown mode");
+        const bool uf = q.mode == SWFE_MODE_UF;
+        if (uf && !(q.uf_p > 0 && q.uf_sigma > 0 && q.uf_T > 0 && q.uf_rcut > 0))
+            return fail(ctx, SWFE_E_INVALID_ARG, "UF reference needs uf_p, uf_sigma, uf_T, uf_rcut > 0");
+        if (uf && q.p_damp > 0) return fail(ctx, SWFE_E_INVALID_ARG, "UF switching runs at fixed volume");
+        const double rmax = uf ? std::max(rc, q.uf_rcut) : rc;
         for (int k = 0; k < 3; ++k)
-            if (!(q.box[k] >= 2.0 * rc)) {
+            if (!(q.box[k] >= 2.0 * rmax)) {
                 snprintf(msg, sizeof msg, "system %d: box length %g below twice the cutoff %g", s,
-                         q.box[k], 2.0 * rc);
+                         q.box[k], 2.0 * rmax);
                 return fail(ctx, SWFE_E_BOX_TOO_SMALL, msg);
             }
-        if (q.mode < 0 || q.mode > 7) return fail(ctx, SWFE_E_INVALID_ARG, "unknown mode");
         if (q.tau_damp < 0 || q.T0 < 0 || q.p_damp < 0)
             return fail(ctx, SWFE_E_INVALID_ARG, "negative T0, tau_damp or p_damp");
         if (q.p_damp > 0 && !(q.T0 > 0))
@@ -175,6 +181,17 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         sd.mode = q.mode;
         sd.partner = is_dcci(q.mode) ? q.partner : -1;
         sd.baro = q.baro;
+        if (uf) {
+            sd.uf_pkT = q.uf_p * kKB * q.uf_T;
+            sd.uf_is2 = 1.0 / (q.uf_sigma * q.uf_sigma);
+            sd.uf_rc = q.uf_rcut;
+            // list capacity for the UF cutoff at this density, allowing skins
+            // up to 1.5 A and 30 % density fluctuation
+            const double rl = std::max(rc, q.uf_rcut) + 1.5;
+            const double dens = (double)q.n_atoms / (q.box[0] * q.box[1] * q.box[2]);
+            const double want = 1.3 * 4.18879020478639 * rl * rl * rl * dens + 16.0;
+            P.list_cap = std::max(P.list_cap, (int32_t)std::min<double>(kMaxListUF, 32.0 * std::ceil(want / 32.0)));
+        }
         // Cell capacity for boxes up to 1.3x the initial length; cells are at
         // least rc + skin >= rc, so rc bounds the count for every skin.
         int64_t cap = 1;
@@ -210,7 +227,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         tiles += (q.n_atoms + 63) / 64;
         off += q.n_atoms;
     }
-    if (off >= ((int64_t)1 << 31) / kMaxList) return fail(ctx, SWFE_E_INVALID_ARG, "too many atoms");
+    if (off >= ((int64_t)1 << 31) / P.list_cap) return fail(ctx, SWFE_E_INVALID_ARG, "too many atoms");
     for (int s = 0; s < n_sys; ++s) {
         Group g{};
         if (is_dcci(d[s].mode)) {
@@ -247,6 +264,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.tx0s = take(d4 * n);
     L.zs = take(d4 * n);
     L.xf = take(sizeof(float4) * n);
+    L.fref = take(d4 * n);
     L.perm = take(4 * n);
     L.tperm = take(4 * n);
     L.norder = take(4 * n);
@@ -255,7 +273,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.nnb = take(4 * n);
     L.cell_count = take(4 * (size_t)cells);
     L.cell_start = take(4 * ((size_t)cells + n_sys));
-    L.nl = take(4 * n * kMaxList);
+    L.nl = take(4 * n * (size_t)P.list_cap);
     L.nl_cnt = take(4 * n);
     L.sl = take(4 * n * kMaxShort);
     L.mom = take(8 * 9 * n);
@@ -311,6 +329,7 @@ Ctl make_ctl(const swfe_ctx *c, int in_step, int flags, int force_rebuild)
     k.dt = c->dt;
     k.seed = c->seed;
     k.flags = flags;
+    k.list_cap = c->plan.list_cap;
     k.in_step = in_step;
     k.force_rebuild = force_rebuild;
     k.log_every = c->log_every;
@@ -394,7 +413,7 @@ int take_device_error(swfe_ctx *c, const std::vector<SysState> &st, hipStream_t 
     HIPCHK(c, hipStreamSynchronize(s));
     char msg[200];
     const char *what = (bits & ERR_NONFINITE) ? "non-finite value"
-                       : (bits & ERR_OVERFLOW) ? "Verlet list overflow (more than 64 within cutoff + skin)"
+                       : (bits & ERR_OVERFLOW) ? "neighbour list overflow (list or short-list capacity exceeded)"
                        : (bits & ERR_BOX) ? "box length fell below twice the cutoff"
                                           : "dCCI update singular (|dv| or denominator too small, or lambda out of (0.05, 20))";
     snprintf(msg, sizeof msg, "system %d: %s", who, what);
@@ -497,6 +516,7 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     q.tx0s = (double4 *)(w + L.tx0s);
     q.zs = (double4 *)(w + L.zs);
     q.xf = (float4 *)(w + L.xf);
+    q.fref = (double4 *)(w + L.fref);
     q.perm = (int32_t *)(w + L.perm);
     q.tperm = (int32_t *)(w + L.tperm);
     q.norder = (int32_t *)(w + L.norder);

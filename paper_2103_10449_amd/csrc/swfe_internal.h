@@ -7,7 +7,8 @@
 
 namespace swfe {
 
-constexpr int kMaxList = 64;       // Verlet-list capacity per atom (within rc + skin)
+constexpr int kMaxList = 64;       // Verlet-list capacity per atom without UF systems
+constexpr int kMaxListUF = 1024;   // largest capacity a UF reference may ask for
 constexpr int kMaxShort = 48;      // neighbours within rc per atom (pass 1 -> pass 2)
 constexpr int kSortThreads = 1024; // threads of the per-system sort workgroup
 constexpr int kNumKernels = 9;     // launches of one dynamics step (for profiling)
@@ -23,6 +24,7 @@ enum : int {
     P_K = 20,       // pass 2: kinetic energy per axis (3)
     P_NOISE = 23,   // pass 2: 3 sums of the next O step's normals
     P_E3 = 19,      // pass 1: three-body energy (slot 19 of the pass-1 row)
+    P_UUF = 20,     // pass 1: Uhlenbeck-Ford reference energy (UF systems)
     kNumPart = 26
 };
 
@@ -31,7 +33,7 @@ enum : int { ERR_OVERFLOW = 1, ERR_NONFINITE = 2, ERR_DCCI = 4, ERR_BOX = 8 };
 
 enum : int {
     MODE_FORCE = 0, MODE_NVE = 1, MODE_NVT = 2, MODE_FL = 3,
-    MODE_RS = 4, MODE_AS_P = 5, MODE_DCCI_T = 6, MODE_DCCI_P = 7
+    MODE_RS = 4, MODE_AS_P = 5, MODE_DCCI_T = 6, MODE_DCCI_P = 7, MODE_UF = 8
 };
 
 struct SwParams {
@@ -49,6 +51,7 @@ struct SysDesc {
     int32_t tile_begin, tile_end; // tiles of this system (contiguous)
     int32_t group;                // reduction group (a system or a dCCI pair)
     int32_t baro;                 // 0: one piston (volume), 1: one piston per axis
+    double uf_pkT, uf_is2, uf_rc; // UF reference: p kB T_UF (eV), 1/sigma^2, cutoff (0: none)
     double k_spring, T0, tau_damp, p_damp;
     double pressure;          // eV/A^3
     double nf;                // 3N - 3
@@ -101,6 +104,7 @@ struct Ctl {
     double dt;
     uint64_t seed;
     int32_t flags;          // PARAM_GRAD / STRAIN
+    int32_t list_cap;       // Verlet-list capacity per atom (rows of nl)
     int32_t in_step;        // 1: the pass belongs to a dynamics step
     int32_t force_rebuild;  // 1: rebuild every system's list now
     int32_t log_every, log_cap;
@@ -124,6 +128,7 @@ struct DevPtrs {
     void *mom;                            // [n_total][9] moments (v, M) in term precision
     double *e_s;                          // per-atom energy, sorted order
     double *part1, *part2;                // [n_tiles][kNumPart]
+    double4 *fref;                        // UF reference force per atom (UF systems), sorted order
     int32_t *work, *n_work;               // tiles to rebuild in this step, and their count
     double *disp_max;                     // [n_sys][2] max squared displacement since build
                                           // (two slots alternate between steps)

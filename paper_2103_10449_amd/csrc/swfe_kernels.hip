@@ -97,7 +97,14 @@ __device__ __forceinline__ void eff_box(const SysState &st, double box[3], doubl
     }
 }
 
-// Cell grid for the list build: cells of at least rc + skin, capped.
+// Radius of a system's Verlet list: the longest interaction cutoff (the SW
+// cutoff, or the UF reference's when longer) plus the skin.
+__device__ __forceinline__ double list_radius(const SwParams &sw, const SysDesc &d)
+{
+    return fmax(sw.rc, d.uf_rc) + d.skin;
+}
+
+// Cell grid for the list build: cells of at least the list radius, capped.
 __device__ __forceinline__ void cell_grid(const SysDesc &d, const double box[3], double rl, int nc[3])
 {
     for (int k = 0; k < 3; ++k) {
@@ -188,11 +195,13 @@ __device__ __forceinline__ bool scales_interaction(int mode)
 }
 
 // Total force component at coupling lam: FL interpolates with the Einstein
-// reference (section 2.1), RS and dCCI scale the interaction (eq. H_RS).
+// reference (section 2.1), UF with the Uhlenbeck-Ford fluid (fref), RS and
+// dCCI scale the interaction (eq. H_RS).
 __device__ __forceinline__ double total_force(int mode, double lam, double fint, double x, double x0,
-                                              double k)
+                                              double k, double fref)
 {
     if (mode == MODE_FL) return lam * fint + (1.0 - lam) * (-k * (x - x0));
+    if (mode == MODE_UF) return lam * fint + (1.0 - lam) * fref;
     if (scales_interaction(mode)) return lam * fint;
     return fint;
 }
@@ -308,7 +317,7 @@ __device__ __forceinline__ void bin_atom(const DevPtrs &p, const SwParams &sw, c
     double box[3], ibox[3];
     int nc[3];
     eff_box(st, box, ibox);
-    cell_grid(d, box, sw.rc + d.skin, nc);
+    cell_grid(d, box, list_radius(sw, d), nc);
     const int cell = cell_of_pos(x, ibox, nc);
     p.cellid[t] = cell;
     p.rank[t] = atomicAdd(&p.cell_count[d.cell_base + cell], 1);
@@ -351,10 +360,11 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
             double4 v = p.vs[t];
             const double4 f = p.fs[t];
             const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
+            const double4 fr = d.mode == MODE_UF ? p.fref[t] : make_double4(0, 0, 0, 0);
             const double hdt = 0.5 * c.dt, ka = hdt * d.acc;
-            v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, f.x, x.x, x0.x, d.k_spring) * st.phi[0];
-            v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, f.y, x.y, x0.y, d.k_spring) * st.phi[1];
-            v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, f.z, x.z, x0.z, d.k_spring) * st.phi[2];
+            v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, f.x, x.x, x0.x, d.k_spring, fr.x) * st.phi[0];
+            v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, f.y, x.y, x0.y, d.k_spring, fr.y) * st.phi[1];
+            v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, f.z, x.z, x0.z, d.k_spring, fr.z) * st.phi[2];
             x.x = x.x * st.grow[0] + (v.x * hdt) * st.psi[0];
             x.y = x.y * st.grow[1] + (v.y * hdt) * st.psi[1];
             x.z = x.z * st.grow[2] + (v.z * hdt) * st.psi[2];
@@ -407,7 +417,7 @@ __device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, i
     double smin = 1e300;
     for (int k = 0; k < 3; ++k) smin = fmin(smin, (st.box[k] * st.pscale[k]) / st.box_build[k]);
     const double shrink = smin < 1.0 ? 1.0 - smin : 0.0;
-    return 2.0 * sqrt(m) + (sw.rc + d.skin) * shrink > d.skin;
+    return 2.0 * sqrt(m) + list_radius(sw, d) * shrink > d.skin;
 }
 
 // Binning of the atoms of every system whose list is stale (each block
@@ -437,7 +447,7 @@ __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwPa
     double box[3], ibox[3];
     int nc3[3];
     eff_box(st, box, ibox);
-    cell_grid(d, box, sw.rc + d.skin, nc3);
+    cell_grid(d, box, list_radius(sw, d), nc3);
     const int nc = nc3[0] * nc3[1] * nc3[2];
     int32_t *cnt = p.cell_count + d.cell_base;
     const int tid = threadIdx.x;
@@ -555,7 +565,7 @@ __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const
     double box[3], ibox[3];
     int nc[3];
     eff_box(st, box, ibox);
-    const double rl = sw.rc + d.skin, rl2 = rl * rl;
+    const double rl = list_radius(sw, d), rl2 = rl * rl;
     cell_grid(d, box, rl, nc);
     const int64_t N = c.n_total;
     const int s = tile.start + (valid ? a_loc : 0);
@@ -566,9 +576,21 @@ __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const
     const int x0c = nc[0] >= 3 ? cx - 1 : 0, y0c = nc[1] >= 3 ? cy - 1 : 0, z0c = nc[2] >= 3 ? cz - 1 : 0;
     const int32_t *start = p.cell_start + d.cell_base + sys;
     const int ncell = nxo * nyo * nzo;
+    // candidates of one chunk of up to 64 atoms of this lane's cell, as a mask
+    auto chunk_mask = [&](int j0, int j1) {
+        unsigned long long m = 0;
+        for (int j = j0; j < j1; ++j) {
+            if (j == s) continue;
+            const double4 xj = p.xs[j];
+            const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
+            const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
+            const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
+            if (dx * dx + dy * dy + dz * dz < rl2) m |= 1ull << (j - j0);
+        }
+        return m;
+    };
     unsigned long long mask = 0;
-    int b = 0, cnt = 0;
-    bool over = false;
+    int b = 0, e = 0, cnt = 0;
     if (valid && lane < ncell) {
         const int ox = lane % nxo, oy = (lane / nxo) % nyo, oz = lane / (nxo * nyo);
         int xx = x0c + ox, yy = y0c + oy, zz = z0c + oz;
@@ -577,18 +599,14 @@ __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const
         zz = zz < 0 ? zz + nc[2] : (zz >= nc[2] ? zz - nc[2] : zz);
         const int cell = (zz * nc[1] + yy) * nc[0] + xx;
         b = start[cell];
-        const int e = start[cell + 1];
-        over = e - b > 64;
-        const int eb = over ? b + 64 : e;
-        for (int j = b; j < eb; ++j) {
-            if (j == s) continue;
-            const double4 xj = p.xs[j];
-            const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
-            const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
-            const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
-            if (dx * dx + dy * dy + dz * dz < rl2) mask |= 1ull << (j - b);
+        e = start[cell + 1];
+        // cells of more than 64 atoms (long UF cutoffs) are counted chunk by
+        // chunk here and re-scanned when the entries are written
+        for (int j0 = b; j0 < e; j0 += 64) {
+            const unsigned long long m = chunk_mask(j0, min(j0 + 64, e));
+            if (j0 == b) mask = m;
+            cnt += __popcll(m);
         }
-        cnt = __popcll(mask);
     }
     // exclusive prefix of the per-cell counts over the 32 lanes of this atom
     int incl = cnt;
@@ -598,15 +616,18 @@ __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const
     }
     const int total = __shfl(incl, 31, 32);
     int slot = incl - cnt;
-    while (mask) {
-        const int k = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        if (slot < kMaxList) p.nl[(int64_t)slot * N + s] = b + k;
-        ++slot;
+    for (int j0 = b; j0 < e; j0 += 64) {
+        unsigned long long m = j0 == b ? mask : chunk_mask(j0, min(j0 + 64, e));
+        while (m) {
+            const int k = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            if (slot < c.list_cap) p.nl[(int64_t)slot * N + s] = j0 + k;
+            ++slot;
+        }
     }
     if (valid) {
-        if (over || total > kMaxList) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
-        if (lane == 0) p.nl_cnt[s] = total < kMaxList ? total : kMaxList;
+        if (total > c.list_cap) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
+        if (lane == 0) p.nl_cnt[s] = total < c.list_cap ? total : c.list_cap;
     }
 }
 
@@ -646,6 +667,7 @@ struct Fm<float> {
     }
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
     static __device__ __forceinline__ float log(float x) { return __logf(x); }
+    static __device__ __forceinline__ float expm1(float x) { return ::expm1f(x); }
 };
 
 template <>
@@ -658,6 +680,7 @@ struct Fm<double> {
     }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
+    static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
 };
 
 // Gather batch sizes: list candidates (filter), short-list neighbours in
@@ -679,10 +702,51 @@ __device__ __forceinline__ int list_entry(const int32_t *list, int k, int n, int
     return k < n ? j : t;
 }
 
+// Uhlenbeck-Ford reference of a UF system (section 4.1; model of Leite et
+// al.): phi(r) = -p kB T ln(1 - exp(-(r/sigma)^2)) over the whole list,
+// half per ordered pair; writes the atom's reference force and adds its
+// energy share to eu.
+template <typename R>
+__device__ __noinline__ void uf_terms(const Ctl &c, const DevPtrs &p, const SysDesc &d, int t, const double4 &xi,
+                                      int cnt, const double box[3], const double ibox[3], double &eu)
+{
+    const int64_t N = c.n_total;
+    const double rc2 = d.uf_rc * d.uf_rc;
+    const R pkT = (R)d.uf_pkT, is2 = (R)d.uf_is2;
+    double fx = 0, fy = 0, fz = 0, e = 0;
+    for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
+        int jb[kBatchA];
+#pragma unroll
+        for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
+        double4 xj[kBatchA];
+#pragma unroll
+        for (int u = 0; u < kBatchA; ++u) xj[u] = p.xs[jb[u]];
+#pragma unroll
+        for (int u = 0; u < kBatchA; ++u) {
+            const double dx = min_image(xj[u].x - xi.x, box[0], ibox[0]);
+            const double dy = min_image(xj[u].y - xi.y, box[1], ibox[1]);
+            const double dz = min_image(xj[u].z - xi.z, box[2], ibox[2]);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (k0 + u >= cnt || !(r2 < rc2)) continue;
+            const R x = (R)r2 * is2;
+            const R em = Fm<R>::exp(-x);
+            const R om = -Fm<R>::expm1(-x);  // 1 - exp(-x)
+            const R phi = -pkT * Fm<R>::log(om);
+            const R g = -pkT * R(2) * is2 * em / om;  // phi'(r) / r
+            fx += (double)(g * (R)dx);
+            fy += (double)(g * (R)dy);
+            fz += (double)(g * (R)dz);
+            e += 0.5 * (double)phi;
+        }
+    }
+    p.fref[t] = make_double4(fx, fy, fz, 0.0);
+    eu = e;
+}
+
 template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 {
-    constexpr int NV = 20;  // E2, virial 9, dtheta 9, E3
+    constexpr int NV = 21;  // E2, virial 9, dtheta 9, E3, U_UF
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -699,6 +763,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const int t = tile.start + threadIdx.x;
         const double4 xi = p.xs[t];
         const int cnt = p.nl_cnt[t];
+        if (p.desc[sys].mode == MODE_UF) uf_terms<R>(c, p, p.desc[sys], t, xi, cnt, box, ibox, acc[P_UUF]);
         // Filter: the list candidates now within rc go to the short list.
         // It is cheap per candidate, so lanes whose candidates are mostly
         // outside rc do not hold the wave in the term evaluation below.
@@ -895,7 +960,8 @@ __device__ double controlled(const SysDesc &d, int64_t k)
 __device__ double h_switch(const SysDesc &d, const SysState &st, double lam, double Ps)
 {
     switch (d.mode) {
-        case MODE_FL: return lam * st.U_int + (1.0 - lam) * st.U_ref;
+        case MODE_FL:
+        case MODE_UF: return lam * st.U_int + (1.0 - lam) * st.U_ref;
         case MODE_RS:
         case MODE_DCCI_T:
         case MODE_DCCI_P: return lam * st.U_int + Ps * st.V;
@@ -963,7 +1029,7 @@ __device__ void next_lambda(const SysDesc &d, const SysState &st, double &lam, d
 {
     lam = st.lam;
     Ps = st.Ps;
-    if (d.mode == MODE_FL) {
+    if (d.mode == MODE_FL || d.mode == MODE_UF) {
         lam = controlled(d, st.k + 1);
         Ps = 0.0;
     } else if (d.mode == MODE_RS) {
@@ -1074,7 +1140,7 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
         st.U_int = st.E2 + st.E3;
         for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
         for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
-        st.U_ref = b[P_UREF];
+        st.U_ref = b[P_UREF] + a[P_UUF];
         for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
         st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
         for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
@@ -1227,9 +1293,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         double4 v = v0;
         if (c.in_step && d.mode != MODE_FORCE) {
             const double ka = (0.5 * c.dt) * d.acc;
-            v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring) * st.phi[0];
-            v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, F.y, xa.y, x0.y, d.k_spring) * st.phi[1];
-            v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, F.z, xa.z, x0.z, d.k_spring) * st.phi[2];
+            const double4 fr = d.mode == MODE_UF ? p.fref[t] : make_double4(0, 0, 0, 0);
+            v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring, fr.x) * st.phi[0];
+            v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, F.y, xa.y, x0.y, d.k_spring, fr.y) * st.phi[1];
+            v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, F.z, xa.z, x0.z, d.k_spring, fr.z) * st.phi[2];
             p.vs[t] = v;
         }
         acc[P_K] = d.mvv2e_m * (v.x * v.x);
@@ -1277,7 +1344,8 @@ __global__ void k_reset_schedule(Ctl c, DevPtrs p)
     const SysDesc &d = p.desc[s];
     SysState &st = p.state[s];
     switch (d.mode) {
-        case MODE_FL: st.lam = d.s_start; st.Ps = 0.0; break;
+        case MODE_FL:
+        case MODE_UF: st.lam = d.s_start; st.Ps = 0.0; break;
         case MODE_RS: st.lam = d.s_start; st.Ps = st.lam * d.pressure; break;
         case MODE_AS_P: st.lam = 1.0; st.Ps = d.s_start / kGpaPerEvA3; break;
         case MODE_DCCI_T: st.lam = d.T0 / d.s_start; st.Ps = st.lam * d.pressure; break;

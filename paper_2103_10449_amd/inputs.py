@@ -176,8 +176,11 @@ def maxwell(n_atoms: int, T: float, g: np.random.Generator,
 # library's: 0 force-only, 1 NVE, 2 NVT, 3 Frenkel-Ladd, 4 reversible scaling,
 # 5 pressure switching, 6 dCCI (temperature control), 7 dCCI (pressure control)
 # ----------------------------------------------------------------------------
-MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P = range(8)
+MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P, MODE_UF = range(9)
 BARO_ISO, BARO_ANISO = 0, 1
+# Uhlenbeck-Ford fluid reference of the liquid (section 4.1): p, sigma (A);
+# the temperature is the run's, the cutoff 4 sigma
+UF_P, UF_SIGMA, UF_RCUT = 25.0, 2.0, 8.0
 
 
 @dataclass
@@ -196,6 +199,10 @@ class SystemSpec:
     pressure: float = 0.0          # physical pressure P, GPa
     stream: int = 0                # noise stream id (Philox key word 1)
     baro: int = 0                  # 0: one piston (volume), 1: one piston per box length
+    uf_p: float = 0.0              # Uhlenbeck-Ford reference (MODE_UF): p, sigma (A), T (K), cutoff (A)
+    uf_sigma: float = 0.0
+    uf_T: float = 0.0
+    uf_rcut: float = 0.0
     # schedule: lam_start/lam_end (FL, RS), or the controlled variable's
     # start/end (P in GPa for pressure switching and dCCI-P, T in K for dCCI-T)
     sched_start: float = 1.0

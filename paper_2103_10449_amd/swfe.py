@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libswfe.so")
 OK = 0
 E_INVALID_ARG, E_BOX_TOO_SMALL, E_OVERFLOW, E_NONFINITE, E_DCCI_SINGULAR, E_HIP, E_STATE, E_NOMEM = \
     -1, -2, -3, -4, -5, -6, -7, -8
-MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P = range(8)
+MODE_FORCE, MODE_NVE, MODE_NVT, MODE_FL, MODE_RS, MODE_AS_P, MODE_DCCI_T, MODE_DCCI_P, MODE_UF = range(9)
 BARO_ISO, BARO_ANISO = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 PARAM_GRAD, STRAIN = 1, 2
@@ -45,7 +45,9 @@ class SystemDesc(ctypes.Structure):
                 ("k_spring", ctypes.c_double), ("T0", ctypes.c_double), ("tau_damp", ctypes.c_double),
                 ("p_damp", ctypes.c_double), ("pressure", ctypes.c_double), ("stream", ctypes.c_uint64),
                 ("sched_start", ctypes.c_double), ("sched_end", ctypes.c_double),
-                ("sched_steps", ctypes.c_int64), ("baro", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sched_steps", ctypes.c_int64), ("baro", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("uf_p", ctypes.c_double), ("uf_sigma", ctypes.c_double), ("uf_T", ctypes.c_double),
+                ("uf_rcut", ctypes.c_double)]
 
 
 class Buffers(ctypes.Structure):
@@ -148,6 +150,10 @@ def system_descs(systems: Sequence) -> "ctypes.Array":
         d.sched_steps = int(getattr(s, "sched_steps", 0))
         d.baro = int(getattr(s, "baro", 0))
         d.reserved = 0
+        d.uf_p = float(getattr(s, "uf_p", 0.0))
+        d.uf_sigma = float(getattr(s, "uf_sigma", 0.0))
+        d.uf_T = float(getattr(s, "uf_T", 0.0))
+        d.uf_rcut = float(getattr(s, "uf_rcut", 0.0))
         off += d.n_atoms
     return arr
 

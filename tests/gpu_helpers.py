@@ -11,7 +11,8 @@ def to_oracle(spec):
                        partner=spec.partner, k_spring=spec.k_spring, T0=spec.T0,
                        tau_damp=spec.tau_damp, p_damp=spec.p_damp, pressure=spec.pressure,
                        stream=spec.stream, sched_start=spec.sched_start, sched_end=spec.sched_end,
-                       sched_steps=spec.sched_steps, baro=getattr(spec, "baro", 0))
+                       sched_steps=spec.sched_steps, baro=getattr(spec, "baro", 0), uf_p=spec.uf_p,
+                       uf_sigma=spec.uf_sigma, uf_T=spec.uf_T, uf_rcut=spec.uf_rcut)
 
 
 def force_err(f, fref):
