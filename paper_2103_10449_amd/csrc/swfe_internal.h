@@ -24,7 +24,7 @@ enum : int {
     P_K = 20,       // pass 2: kinetic energy per axis (3)
     P_NOISE = 23,   // pass 2: 3 sums of the next O step's normals
     P_E3 = 19,      // pass 1: three-body energy (slot 19 of the pass-1 row)
-    P_UUF = 20,     // pass 1: Uhlenbeck-Ford reference energy (UF systems)
+    P_UUF = 20,     // pass-1 row: Uhlenbeck-Ford reference energy (UF kernel)
     kNumPart = 26
 };
 
@@ -105,6 +105,7 @@ struct Ctl {
     uint64_t seed;
     int32_t flags;          // PARAM_GRAD / STRAIN
     int32_t list_cap;       // Verlet-list capacity per atom (rows of nl)
+    int32_t has_uf;         // 1: some system switches to the UF reference
     int32_t in_step;        // 1: the pass belongs to a dynamics step
     int32_t force_rebuild;  // 1: rebuild every system's list now
     int32_t log_every, log_cap;

@@ -702,51 +702,10 @@ __device__ __forceinline__ int list_entry(const int32_t *list, int k, int n, int
     return k < n ? j : t;
 }
 
-// Uhlenbeck-Ford reference of a UF system (section 4.1; model of Leite et
-// al.): phi(r) = -p kB T ln(1 - exp(-(r/sigma)^2)) over the whole list,
-// half per ordered pair; writes the atom's reference force and adds its
-// energy share to eu.
-template <typename R>
-__device__ __noinline__ void uf_terms(const Ctl &c, const DevPtrs &p, const SysDesc &d, int t, const double4 &xi,
-                                      int cnt, const double box[3], const double ibox[3], double &eu)
-{
-    const int64_t N = c.n_total;
-    const double rc2 = d.uf_rc * d.uf_rc;
-    const R pkT = (R)d.uf_pkT, is2 = (R)d.uf_is2;
-    double fx = 0, fy = 0, fz = 0, e = 0;
-    for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
-        int jb[kBatchA];
-#pragma unroll
-        for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
-        double4 xj[kBatchA];
-#pragma unroll
-        for (int u = 0; u < kBatchA; ++u) xj[u] = p.xs[jb[u]];
-#pragma unroll
-        for (int u = 0; u < kBatchA; ++u) {
-            const double dx = min_image(xj[u].x - xi.x, box[0], ibox[0]);
-            const double dy = min_image(xj[u].y - xi.y, box[1], ibox[1]);
-            const double dz = min_image(xj[u].z - xi.z, box[2], ibox[2]);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (k0 + u >= cnt || !(r2 < rc2)) continue;
-            const R x = (R)r2 * is2;
-            const R em = Fm<R>::exp(-x);
-            const R om = -Fm<R>::expm1(-x);  // 1 - exp(-x)
-            const R phi = -pkT * Fm<R>::log(om);
-            const R g = -pkT * R(2) * is2 * em / om;  // phi'(r) / r
-            fx += (double)(g * (R)dx);
-            fy += (double)(g * (R)dy);
-            fz += (double)(g * (R)dz);
-            e += 0.5 * (double)phi;
-        }
-    }
-    p.fref[t] = make_double4(fx, fy, fz, 0.0);
-    eu = e;
-}
-
 template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 {
-    constexpr int NV = 21;  // E2, virial 9, dtheta 9, E3, U_UF
+    constexpr int NV = 20;  // E2, virial 9, dtheta 9, E3
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -763,7 +722,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const int t = tile.start + threadIdx.x;
         const double4 xi = p.xs[t];
         const int cnt = p.nl_cnt[t];
-        if (p.desc[sys].mode == MODE_UF) uf_terms<R>(c, p, p.desc[sys], t, xi, cnt, box, ibox, acc[P_UUF]);
         // Filter: the list candidates now within rc go to the short list.
         // It is cheap per candidate, so lanes whose candidates are mostly
         // outside rc do not hold the wave in the term evaluation below.
@@ -912,6 +870,63 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         p.e_s[t] = acc[0] + acc[19];
     }
     block_reduce<NV>(acc, p.part1 + (int64_t)ti * kNumPart);
+}
+
+// ------------------------------------------------------ UF reference ---
+// Uhlenbeck-Ford reference of the UF systems (section 4.1; model of Leite et
+// al.): phi(r) = -p kB T ln(1 - exp(-(r/sigma)^2)) over each atom's whole
+// list, half per ordered pair.  Writes the reference force of every atom and
+// the tile's energy into its pass-1 row.  Launched only when a UF system is
+// present; other tiles leave at once.
+template <typename R>
+__global__ void __launch_bounds__(256) k_uf(Ctl c, DevPtrs p)
+{
+    const int ti = tile_of_block(c);
+    if (ti < 0) return;
+    const Tile tile = p.tiles[ti];
+    const SysDesc &d = p.desc[tile.sys];
+    if (d.mode != MODE_UF) return;
+    const SysState &st = p.state[tile.sys];
+    const int64_t N = c.n_total;
+    double e = 0.0;
+    if ((int)threadIdx.x < tile.count) {
+        double box[3], ibox[3];
+        eff_box(st, box, ibox);
+        const int t = tile.start + threadIdx.x;
+        const double4 xi = p.xs[t];
+        const int cnt = p.nl_cnt[t];
+        const double rc2 = d.uf_rc * d.uf_rc;
+        const R pkT = (R)d.uf_pkT, is2 = (R)d.uf_is2;
+        double fx = 0, fy = 0, fz = 0;
+        for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
+            int jb[kBatchA];
+#pragma unroll
+            for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
+            double4 xj[kBatchA];
+#pragma unroll
+            for (int u = 0; u < kBatchA; ++u) xj[u] = p.xs[jb[u]];
+#pragma unroll
+            for (int u = 0; u < kBatchA; ++u) {
+                const double dx = min_image(xj[u].x - xi.x, box[0], ibox[0]);
+                const double dy = min_image(xj[u].y - xi.y, box[1], ibox[1]);
+                const double dz = min_image(xj[u].z - xi.z, box[2], ibox[2]);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (k0 + u >= cnt || !(r2 < rc2)) continue;
+                const R x = (R)r2 * is2;
+                const R em = Fm<R>::exp(-x);
+                const R om = -Fm<R>::expm1(-x);  // 1 - exp(-x)
+                const R phi = -pkT * Fm<R>::log(om);
+                const R g = -pkT * R(2) * is2 * em / om;  // phi'(r) / r
+                fx += (double)(g * (R)dx);
+                fy += (double)(g * (R)dy);
+                fz += (double)(g * (R)dz);
+                e += 0.5 * (double)phi;
+            }
+        }
+        p.fref[t] = make_double4(fx, fy, fz, 0.0);
+    }
+    double acc[1] = {e};
+    block_reduce<1>(acc, p.part1 + (int64_t)ti * kNumPart + P_UUF);
 }
 
 // ---------------------------------------------------------------- pass 2 ---
@@ -1140,7 +1155,7 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
         st.U_int = st.E2 + st.E3;
         for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
         for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
-        st.U_ref = b[P_UREF] + a[P_UUF];
+        st.U_ref = b[P_UREF] + (d.mode == MODE_UF ? a[P_UUF] : 0.0);
         for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
         st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
         for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
@@ -1429,6 +1444,10 @@ hipError_t launch_pass1(const Ctl &c, const DevPtrs &p, const SwParams &sw, int 
     } else {
         if (g) hipLaunchKernelGGL((k_pass1<double, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
         else hipLaunchKernelGGL((k_pass1<double, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+    }
+    if (c.has_uf) {
+        if (mixed) hipLaunchKernelGGL((k_uf<float>), tile_grid(c), dim3(block), 0, s, c, p);
+        else hipLaunchKernelGGL((k_uf<double>), tile_grid(c), dim3(block), 0, s, c, p);
     }
     return hipGetLastError();
 }
