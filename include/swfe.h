@@ -266,6 +266,26 @@ int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)
 int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom,
                         int64_t *list_entries, void *stream);
 
+/* ---- checkpoint / resume ---------------------------------------------------
+ * A checkpoint is a host byte blob holding the context's settings (SW
+ * parameters, descriptors with their current schedules, seed, time step,
+ * precision, block size, skin, log settings), the whole workspace (the
+ * cell-sorted atom data, lists, stored normals, per-system switching and
+ * barostat state, the log ring) and the caller's x, v and f.  Loading it
+ * into a context initialised with descriptors of the same system sizes and
+ * buffers of the same sizes resumes the run bitwise: the noise is
+ * counter-based (step, atom) and every sum has a fixed order.
+ *
+ * swfe_checkpoint_bytes: size of the blob (host output).
+ * swfe_save_state: writes the blob to host memory of at least that size;
+ *   synchronises the stream.
+ * swfe_load_state: restores a blob written by swfe_save_state of a context
+ *   with the same system sizes; SWFE_E_INVALID_ARG when the blob does not
+ *   belong to such a context (bad magic, version, sizes); synchronises. */
+int swfe_checkpoint_bytes(const swfe_ctx *ctx, size_t *bytes);
+int swfe_save_state(swfe_ctx *ctx, void *host, size_t bytes, void *stream);
+int swfe_load_state(swfe_ctx *ctx, const void *host, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

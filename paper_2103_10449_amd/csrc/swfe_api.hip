@@ -898,3 +898,127 @@ int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_at
 }
 
 }  // extern "C"
+
+// ---- checkpoint / resume ----------------------------------------------------
+namespace {
+
+struct CkptHeader {
+    char magic[8];
+    int32_t version, n_sys;
+    int64_t n_total;
+    uint64_t ws_bytes;
+    int32_t block, mixed;
+    double skin, dt;
+    uint64_t seed;
+    int32_t log_every, log_cap;
+    swfe_sw_params sw;
+};
+
+constexpr char kCkptMagic[8] = {'S', 'W', 'F', 'E', 'C', 'K', 'P', 'T'};
+
+size_t ckpt_bytes(const swfe_ctx *c)
+{
+    return sizeof(CkptHeader) + sizeof(swfe_system_desc) * (size_t)c->n_sys + c->plan.lay.total +
+           3 * sizeof(double) * 3 * (size_t)c->n_total;
+}
+
+}  // namespace
+
+int swfe_checkpoint_bytes(const swfe_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !ctx->ready) return SWFE_E_STATE;
+    if (!bytes) return SWFE_E_INVALID_ARG;
+    *bytes = ckpt_bytes(ctx);
+    return SWFE_OK;
+}
+
+int swfe_save_state(swfe_ctx *ctx, void *host, size_t bytes, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!host || bytes < ckpt_bytes(ctx)) return fail(ctx, SWFE_E_INVALID_ARG, "checkpoint buffer too small");
+    hipStream_t s = (hipStream_t)stream;
+    char *o = (char *)host;
+    CkptHeader hd{};
+    memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1;
+    hd.n_sys = ctx->n_sys;
+    hd.n_total = ctx->n_total;
+    hd.ws_bytes = ctx->plan.lay.total;
+    hd.block = ctx->block;
+    hd.mixed = ctx->mixed;
+    hd.skin = ctx->skin;
+    hd.dt = ctx->dt;
+    hd.seed = ctx->seed;
+    hd.log_every = ctx->log_every;
+    hd.log_cap = ctx->log_cap;
+    hd.sw = ctx->hsw;
+    memcpy(o, &hd, sizeof hd);
+    o += sizeof hd;
+    // descriptors with the schedules now in force
+    std::vector<swfe_system_desc> dsc = ctx->hdesc;
+    for (int i = 0; i < ctx->n_sys; ++i) {
+        dsc[i].sched_start = ctx->plan.desc[i].s_start;
+        dsc[i].sched_end = ctx->plan.desc[i].s_end;
+        dsc[i].sched_steps = ctx->plan.desc[i].s_steps;
+    }
+    memcpy(o, dsc.data(), sizeof(swfe_system_desc) * ctx->n_sys);
+    o += sizeof(swfe_system_desc) * ctx->n_sys;
+    HIPCHK(ctx, hipMemcpyAsync(o, ctx->buf.workspace, ctx->plan.lay.total, hipMemcpyDeviceToHost, s));
+    o += ctx->plan.lay.total;
+    const size_t n3 = 3 * sizeof(double) * (size_t)ctx->n_total;
+    HIPCHK(ctx, hipMemcpyAsync(o, ctx->buf.x, n3, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(o + n3, ctx->buf.v, n3, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(o + 2 * n3, ctx->buf.f, n3, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return SWFE_OK;
+}
+
+int swfe_load_state(swfe_ctx *ctx, const void *host, size_t bytes, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    if (!host || bytes < sizeof(CkptHeader)) return fail(ctx, SWFE_E_INVALID_ARG, "checkpoint too short");
+    CkptHeader hd;
+    memcpy(&hd, host, sizeof hd);
+    if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+        return fail(ctx, SWFE_E_INVALID_ARG, "not a checkpoint of this library version");
+    if (hd.n_sys != ctx->n_sys || hd.n_total != ctx->n_total || bytes < ckpt_bytes(ctx))
+        return fail(ctx, SWFE_E_INVALID_ARG, "checkpoint of a context with other system sizes");
+    const char *in = (const char *)host + sizeof hd;
+    std::vector<swfe_system_desc> dsc(ctx->n_sys);
+    memcpy(dsc.data(), in, sizeof(swfe_system_desc) * ctx->n_sys);
+    in += sizeof(swfe_system_desc) * ctx->n_sys;
+    for (int i = 0; i < ctx->n_sys; ++i)
+        if (dsc[i].n_atoms != ctx->hdesc[i].n_atoms)
+            return fail(ctx, SWFE_E_INVALID_ARG, "checkpoint of a context with other system sizes");
+    Plan P;
+    RCHK(plan_systems(ctx, dsc.data(), ctx->n_sys, &hd.sw, hd.dt, hd.skin, P));
+    if (P.lay.total != hd.ws_bytes || P.lay.total > ctx->buf.workspace_bytes)
+        return fail(ctx, SWFE_E_INVALID_ARG, "checkpoint workspace layout differs from this context's");
+    for (int s = 0; s < ctx->n_sys; ++s)
+        if (dsc[s].mode == SWFE_MODE_FL && !ctx->buf.x0)
+            return fail(ctx, SWFE_E_INVALID_ARG, "Frenkel-Ladd systems need Einstein anchors x0");
+    hipStream_t s = (hipStream_t)stream;
+    drop_graph(ctx);
+    ctx->plan = std::move(P);
+    ctx->hdesc = dsc;
+    ctx->hsw = hd.sw;
+    ctx->sw = make_sw(hd.sw);
+    ctx->mixed = hd.mixed;
+    ctx->dt = hd.dt;
+    ctx->seed = hd.seed;
+    ctx->skin = hd.skin;
+    ctx->block = hd.block;
+    ctx->log_every = hd.log_every;
+    ctx->log_cap = hd.log_cap;
+    build_tiles(ctx);
+    // the device tables, atom data and state come back with the workspace
+    HIPCHK(ctx, hipMemcpyAsync(ctx->buf.workspace, in, ctx->plan.lay.total, hipMemcpyHostToDevice, s));
+    in += ctx->plan.lay.total;
+    const size_t n3 = 3 * sizeof(double) * (size_t)ctx->n_total;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->buf.x, in, n3, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->buf.v, in + n3, n3, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->buf.f, in + 2 * n3, n3, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return SWFE_OK;
+}
+

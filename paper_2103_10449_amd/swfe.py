@@ -69,7 +69,7 @@ EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_byt
            "swfe_build_neighbors", "swfe_compute_forces", "swfe_set_schedule", "swfe_step_switched",
            "swfe_work_integral", "swfe_get_state", "swfe_set_log", "swfe_read_log", "swfe_set_block",
            "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats", "swfe_set_skin",
-           "swfe_set_params")
+           "swfe_set_params", "swfe_checkpoint_bytes", "swfe_save_state", "swfe_load_state")
 KERNEL_NAMES = ("integrate", "rebuild_count", "rebuild_scan", "rebuild_scatter", "rebuild_order",
                 "rebuild_list", "pass1", "pass2", "finalize")
 
@@ -107,6 +107,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "swfe_autotune": ([vp, ctypes.POINTER(i32), vp], ctypes.c_int),
         "swfe_sizes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32)], ctypes.c_int),
         "swfe_profile_steps": ([vp, i64, dp, vp], ctypes.c_int),
+        "swfe_checkpoint_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "swfe_save_state": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "swfe_load_state": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "swfe_neighbor_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64), vp],
                                 ctypes.c_int),
         "swfe_set_skin": ([vp, ctypes.c_double, vp], ctypes.c_int),
@@ -318,6 +321,22 @@ class Engine:
         self._check(self.lib.swfe_neighbor_stats(self.ctx, ctypes.byref(tot), ctypes.byref(mx),
                                                  ctypes.byref(ll), self._stream()))
         return int(tot.value), int(mx.value), int(ll.value)
+
+    def save_state(self) -> np.ndarray:
+        """Checkpoint of the whole run state as a host byte array (the library
+        blob: settings, workspace, x, v, f)."""
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.swfe_checkpoint_bytes(self.ctx, ctypes.byref(n)))
+        blob = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.swfe_save_state(self.ctx, blob.ctypes.data_as(ctypes.c_void_p), n.value,
+                                             self._stream()))
+        return blob
+
+    def load_state(self, blob: np.ndarray):
+        """Resume from a checkpoint of a context with the same system sizes."""
+        blob = np.ascontiguousarray(blob, dtype=np.uint8)
+        self._check(self.lib.swfe_load_state(self.ctx, blob.ctypes.data_as(ctypes.c_void_p), blob.size,
+                                             self._stream()))
 
     def set_skin(self, skin: float):
         self._check(self.lib.swfe_set_skin(self.ctx, float(skin), self._stream()))
