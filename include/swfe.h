@@ -230,8 +230,10 @@ int swfe_work_integral(swfe_ctx *ctx, double *W, double *lam, double *Ps, int64_
 int swfe_get_state(swfe_ctx *ctx, swfe_system_state *out, void *stream);
 
 /* Copy of the log ring: every log_every steps one row per system of
- * (step, lambda, P_S GPa, P GPa, T K, U_int/N, V/N, W).  swfe_set_log sets
- * log_every (0 disables) and the ring capacity in rows. */
+ * (step, lambda, P_S GPa, P GPa, T K, U_int/N, V/N, W), P = P_S / lambda and
+ * T the kinetic temperature.  Rows come oldest logging event first and, within
+ * an event, in system order (row r belongs to system r mod n_sys).
+ * swfe_set_log sets log_every (0 disables) and the ring capacity in rows. */
 #define SWFE_LOG_STRIDE 8
 int swfe_set_log(swfe_ctx *ctx, int32_t log_every, int32_t capacity);
 int swfe_read_log(swfe_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows, void *stream);

@@ -1,0 +1,76 @@
+"""Host-side estimators of the switching methods (section 2 and 3): free
+energies from forward/backward dynamical work, the reversible-scaling
+Gibbs curve G(T), the pressure-switching Gibbs curve G(P), and the dCCI
+coexistence line.  Plain numpy on logged (lambda, work) or (P, work)
+trajectories; they do no dynamics."""
+from typing import Sequence, Tuple
+
+import numpy as np
+
+KB = 8.617333262e-5  # eV/K
+
+
+def delta_f(w_forward, w_backward) -> float:
+    """F(b) - F(a) = (mean W(a->b) - mean W(b->a)) / 2 (eq. dF)."""
+    return 0.5 * (float(np.mean(w_forward)) - float(np.mean(w_backward)))
+
+
+def dissipated_heat(w_forward, w_backward) -> float:
+    """Mean dissipated heat (mean W(a->b) + mean W(b->a)) / 2 (eq. Qdiss)."""
+    return 0.5 * (float(np.mean(w_forward)) + float(np.mean(w_backward)))
+
+
+def _work_along(x_log: np.ndarray, w_log: np.ndarray, grid: np.ndarray) -> np.ndarray:
+    """Accumulated work at the grid values of the switched variable, from a
+    monotone logged path (x, W)."""
+    x_log, w_log = np.asarray(x_log, float), np.asarray(w_log, float)
+    order = np.argsort(x_log)
+    return np.interp(grid, x_log[order], w_log[order])
+
+
+def gibbs_rs(G0: float, n_atoms: int, T0: float, lam_fwd, w_fwd, lam_bwd, w_bwd, lam_grid) -> Tuple[np.ndarray, np.ndarray]:
+    """Gibbs free energy G(P, T0/lambda) on lam_grid from reversible scaling
+    (eq. Gibbs_RS): G0/lambda + (3/2) N kB T0 ln(lambda)/lambda +
+    [W(1->lambda) - W(lambda->1)] / (2 lambda).
+
+    lam_fwd, w_fwd: the logged lambda and accumulated work of a run from 1
+    to lambda_f (W = 0 at lambda = 1); lam_bwd, w_bwd: those of the run back
+    from lambda_f to 1.  W(lambda->1) is the backward total minus the
+    backward work done before reaching lambda.  Returns (T, G)."""
+    lam = np.asarray(lam_grid, float)
+    lam_b = np.asarray(lam_bwd, float)
+    w_b = np.asarray(w_bwd, float)
+    wf = _work_along(np.r_[1.0, np.asarray(lam_fwd, float)], np.r_[0.0, np.asarray(w_fwd, float)], lam)
+    wb_total = float(w_b[-1])
+    wb_before = _work_along(np.r_[lam_b[0] if len(lam_b) else 1.0, lam_b], np.r_[0.0, w_b], lam)
+    wb = wb_total - wb_before
+    G = G0 / lam + 1.5 * n_atoms * KB * T0 * np.log(lam) / lam + (wf - wb) / (2.0 * lam)
+    return T0 / lam, G
+
+
+def gibbs_as(G0: float, p_fwd, w_fwd, p_bwd, w_bwd, p_grid) -> Tuple[np.ndarray, np.ndarray]:
+    """Gibbs free energy G(P, T) on p_grid from pressure switching (eq.
+    Gibbs_AS): G0 + [W(P0->P) - W(P->P0)] / 2, with W = int dP/dt V dt (eq.
+    Wmech_dyn) logged along the forward run P0 -> P1 and the backward run
+    P1 -> P0 (pressures in the units of the work's P V, e.g. eV/A^3 with V
+    in A^3).  Returns (P, G)."""
+    p = np.asarray(p_grid, float)
+    pb = np.asarray(p_bwd, float)
+    wb = np.asarray(w_bwd, float)
+    p0 = float(np.asarray(p_fwd, float)[0])
+    wf = _work_along(np.r_[p0, np.asarray(p_fwd, float)], np.r_[0.0, np.asarray(w_fwd, float)], p)
+    wb_before = _work_along(np.r_[pb[0], pb], np.r_[0.0, wb], p)
+    return p, G0 + 0.5 * (wf - (float(wb[-1]) - wb_before))
+
+
+def einstein_free_energy_difference(k1: float, k2: float, T: float, n_atoms: int) -> float:
+    """F(k2) - F(k1) of a classical Einstein crystal of n_atoms 3D oscillators
+    at temperature T: (3 n / 2) kB T ln(k2 / k1)."""
+    return 1.5 * n_atoms * KB * T * np.log(k2 / k1)
+
+
+def dcci_coexistence(T0: float, lam: Sequence[float], Ps: Sequence[float]) -> Tuple[np.ndarray, np.ndarray]:
+    """Points (T, P) of a dCCI coexistence line from the logged coupling
+    (section 3): T = T0 / lambda, P = P_S / lambda."""
+    lam = np.asarray(lam, float)
+    return T0 / lam, np.asarray(Ps, float) / lam

@@ -301,6 +301,11 @@ class Engine:
         self._check(self.lib.swfe_read_log(self.ctx, _dp(rows), max_rows, ctypes.byref(n), self._stream()))
         return rows[:n.value]
 
+    def read_log_by_system(self, max_rows: int = 16384) -> List[np.ndarray]:
+        """The log split per system: rows (step, lambda, P_S, P, T, U/N, V/N, W)."""
+        rows = self.read_log(max_rows)
+        return [rows[k::self.n_sys] for k in range(self.n_sys)]
+
     def set_block(self, block: int):
         self._check(self.lib.swfe_set_block(self.ctx, int(block), self._stream()))
 
@@ -364,11 +369,4 @@ class Engine:
 # Host estimators (section 2): the same formulas the oracle uses, written
 # here independently for library users.
 # ---------------------------------------------------------------------------
-def delta_f(w_forward, w_backward) -> float:
-    """F(lambda_f) - F(lambda_i) from forward/backward work means (eq. dF)."""
-    return 0.5 * (float(np.mean(w_forward)) - float(np.mean(w_backward)))
-
-
-def dissipated_heat(w_forward, w_backward) -> float:
-    """Mean dissipated heat of either direction (eq. Qdiss)."""
-    return 0.5 * (float(np.mean(w_forward)) + float(np.mean(w_backward)))
+from .estimators import delta_f, dissipated_heat  # noqa: E402,F401  (eqs. dF, Qdiss)

@@ -1,0 +1,84 @@
+"""Host estimators of the product package (paper_2103_10449_amd.estimators)
+against closed forms and against the oracle's own estimators."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2103_10449_amd import estimators as est
+
+KB = 8.617333262e-5
+
+
+def test_delta_f_and_heat_match_oracle():
+    g = np.random.default_rng(3)
+    wf, wb = g.normal(1.0, 0.1, 50), g.normal(-0.7, 0.1, 40)
+    assert est.delta_f(wf, wb) == pytest.approx(orc.delta_f(wf, wb), abs=0, rel=1e-15)
+    assert est.dissipated_heat(wf, wb) == pytest.approx(orc.q_diss(wf, wb), rel=1e-15)
+    assert est.einstein_free_energy_difference(2.0, 7.0, 300.0, 64) == pytest.approx(
+        orc.einstein_free_energy_difference(2.0, 7.0, 300.0, 64), rel=1e-15)
+
+
+def _rs_harmonic_paths(n_atoms, T0, lam_f, n):
+    """Quasi-static reversible-scaling work of a classical harmonic crystal:
+    with H = lambda U at T0, <U> = 3 N kB T0 / (2 lambda), so the work from 1
+    to lambda is (3/2) N kB T0 ln(lambda) and the way back returns it."""
+    lam_fwd = np.linspace(1.0, lam_f, n)
+    w_fwd = 1.5 * n_atoms * KB * T0 * np.log(lam_fwd)
+    lam_bwd = lam_fwd[::-1]
+    w_bwd = 1.5 * n_atoms * KB * T0 * (np.log(lam_bwd) - np.log(lam_f))
+    return lam_fwd, w_fwd, lam_bwd, w_bwd
+
+
+def test_gibbs_rs_reproduces_harmonic_free_energy():
+    """A classical harmonic crystal has F(T) = 3 N kB T ln(c / T); reversible
+    scaling from F(T0) must give F(T0/lambda) for every lambda (eq. Gibbs_RS).
+    Dropping the kinetic (3/2) N kB T0 ln(lambda) term or the 1/lambda of the
+    work term misses it by O(N kB T0)."""
+    N, T0, c = 64, 600.0, 5.0e4
+    F = lambda T: 3 * N * KB * T * np.log(c / T)
+    lf, wf, lb, wb = _rs_harmonic_paths(N, T0, 2.5, 4001)
+    grid = np.linspace(1.0, 2.5, 13)
+    T, G = est.gibbs_rs(F(T0), N, T0, lf, wf, lb, wb, grid)
+    np.testing.assert_allclose(T, T0 / grid, rtol=1e-15)
+    np.testing.assert_allclose(G, F(T), rtol=0, atol=2e-6)
+    # each grid point agrees with the oracle's single-lambda formula
+    for lam, g in zip(grid, G):
+        wfl = 1.5 * N * KB * T0 * np.log(lam)
+        assert g == pytest.approx(orc.gibbs_rs(F(T0), lam, N, T0, wfl, -wfl), abs=2e-6)
+
+
+def test_gibbs_rs_uses_the_backward_work_from_lambda_to_one():
+    """Irreversible paths: W(1->lambda) of the forward run and W(lambda->1) =
+    W_b(total) - W_b(up to lambda) of the backward run."""
+    N, T0 = 10, 300.0
+    lf = np.linspace(1.0, 2.0, 101)
+    wf = 0.3 * (lf - 1.0) + 0.05 * (lf - 1.0) ** 2
+    lb = lf[::-1]
+    wb = -0.2 * (2.0 - lb) + 0.01 * (2.0 - lb) ** 3
+    lam = 1.6
+    _, G = est.gibbs_rs(-1.0, N, T0, lf, wf, lb, wb, [lam])
+    w_f = 0.3 * 0.6 + 0.05 * 0.36
+    w_b_to_lam = -0.2 * 0.4 + 0.01 * 0.064
+    w_b_total = -0.2 + 0.01
+    expect = orc.gibbs_rs(-1.0, lam, N, T0, w_f, w_b_total - w_b_to_lam)
+    assert G[0] == pytest.approx(expect, abs=5e-6)
+
+
+def test_gibbs_as_reproduces_ideal_gas():
+    """Quasi-static pressure switching of an ideal gas: W = int V dP with
+    V = N kB T / P, so G(P) - G(P0) = N kB T ln(P / P0) (eq. Gibbs_AS)."""
+    N, T, P0, P1 = 100, 800.0, 0.01, 0.05
+    pf = np.linspace(P0, P1, 20001)
+    wf = N * KB * T * np.log(pf / P0)
+    pb = pf[::-1]
+    wb = N * KB * T * np.log(pb / P1)
+    grid = np.linspace(P0, P1, 9)
+    P, G = est.gibbs_as(-3.0, pf, wf, pb, wb, grid)
+    np.testing.assert_allclose(P, grid)
+    np.testing.assert_allclose(G, -3.0 + N * KB * T * np.log(grid / P0), atol=1e-9)
+
+
+def test_dcci_coexistence_scaling():
+    T, P = est.dcci_coexistence(1000.0, [1.0, 2.0, 0.5], [3.0, 3.0, 1.0])
+    np.testing.assert_allclose(T, [1000.0, 500.0, 2000.0])
+    np.testing.assert_allclose(P, [3.0, 1.5, 2.0])
