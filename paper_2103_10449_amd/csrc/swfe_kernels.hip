@@ -1085,53 +1085,70 @@ __device__ void step_factors(const SysDesc &d, SysState &st, double dt, double r
         if (!(st.box[k] >= 2.0 * rc)) st.err |= ERR_BOX;
 }
 
-// Start of a step for a group: switch (1), barostat half step (2), factors.
-__device__ void group_start_step(const Ctl &c, const DevPtrs &p, const SwParams &sw, const Group &G)
+// Start of a step for a group (one system, or a dCCI pair when d1 and s1
+// are given): switch (1), barostat half step (2), factors.
+__device__ void group_start_step(const Ctl &c, const SwParams &sw, const SysDesc &d0, SysState &s0,
+                                 const SysDesc *d1, SysState *s1)
 {
-    const SysDesc &d0 = p.desc[G.s0];
-    SysState &s0 = p.state[G.s0];
-    double lam[2], Ps[2];
-    if (G.s1 >= 0) {
-        double l, P;
-        if (!dcci_next(d0, s0, p.desc[G.s1], p.state[G.s1], l, P)) {
+    double lam, Ps;
+    if (s1) {
+        if (!dcci_next(d0, s0, *d1, *s1, lam, Ps)) {
             s0.err |= ERR_DCCI;
-            p.state[G.s1].err |= ERR_DCCI;
+            s1->err |= ERR_DCCI;
         }
-        lam[0] = lam[1] = l;
-        Ps[0] = Ps[1] = P;
     } else {
-        next_lambda(d0, s0, lam[0], Ps[0]);
+        next_lambda(d0, s0, lam, Ps);
     }
-    for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
-        const int s = q == 0 ? G.s0 : G.s1;
-        apply_switch(p.desc[s], p.state[s], lam[q], Ps[q]);
-        baro_half(p.desc[s], p.state[s], c.dt);
-        step_factors(p.desc[s], p.state[s], c.dt, sw.rc);
+    apply_switch(d0, s0, lam, Ps);
+    baro_half(d0, s0, c.dt);
+    step_factors(d0, s0, c.dt, sw.rc);
+    if (s1) {
+        apply_switch(*d1, *s1, lam, Ps);
+        baro_half(*d1, *s1, c.dt);
+        step_factors(*d1, *s1, c.dt, sw.rc);
     }
 }
 
+// Cooperative copy of n bytes (a multiple of 4) by the threads of a block.
+__device__ __forceinline__ void block_copy(void *dst, const void *src, int n)
+{
+    for (int w = threadIdx.x; w < n / 4; w += blockDim.x)
+        static_cast<int32_t *>(dst)[w] = static_cast<const int32_t *>(src)[w];
+}
+
 // Reductions of one group over its tiles in a fixed order (all threads of
-// the block), then the scalar update by thread 0.
+// the block), then the scalar update by thread 0 on copies of the group's
+// descriptors and states held in LDS (one load and one store of each field
+// instead of a chain of dependent global accesses), written back at the end.
 __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &sw, const Group &G)
 {
+    static_assert(sizeof(SysState) % 4 == 0 && sizeof(SysDesc) % 4 == 0, "word copies");
     __shared__ double red[4][64];
     __shared__ double sums[2][2 * kNumPart];
+    __shared__ SysState sst[2];
+    __shared__ SysDesc sdesc[2];
+    const int nq = G.s1 >= 0 ? 2 : 1;
+    const int sid[2] = {G.s0, G.s1};
+    for (int q = 0; q < nq; ++q) {
+        block_copy(&sst[q], &p.state[sid[q]], sizeof(SysState));
+        block_copy(&sdesc[q], &p.desc[sid[q]], sizeof(SysDesc));
+    }
     const int k = threadIdx.x & 63, j = threadIdx.x >> 6, nj = blockDim.x >> 6;
-    for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
-        const SysDesc &d = p.desc[q == 0 ? G.s0 : G.s1];
+    for (int q = 0; q < nq; ++q) {
+        const SysDesc &d = p.desc[sid[q]];
         double a = 0.0;
         if (k < 2 * kNumPart) {
             const double *src = k < kNumPart ? p.part1 + k : p.part2 + (k - kNumPart);
-            // eight independent loads in flight per round, summed in a fixed order
-            int t = d.tile_begin + j;
-            for (; t + 7 * nj < d.tile_end; t += 8 * nj) {
-                double v[8];
+            // rounds of sixteen independent loads in flight (the last one
+            // padded with zeros), summed in a fixed order
+            for (int t = d.tile_begin + j; t < d.tile_end; t += 16 * nj) {
+                double v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(t + u * nj) * kNumPart];
+                for (int u = 0; u < 16; ++u)
+                    v[u] = t + u * nj < d.tile_end ? src[(int64_t)(t + u * nj) * kNumPart] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a += v[u];
+                for (int u = 0; u < 16; ++u) a += v[u];
             }
-            for (; t < d.tile_end; t += nj) a += src[(int64_t)t * kNumPart];
         }
         red[j][k] = a;
         __syncthreads();
@@ -1142,57 +1159,61 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    const bool step_end = c.in_step != 0;
-    int64_t remaining = 0;
-    for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
-        const int s = q == 0 ? G.s0 : G.s1;
-        const SysDesc &d = p.desc[s];
-        SysState &st = p.state[s];
-        const double *a = sums[q], *b = sums[q] + kNumPart;
-        st.E2 = a[P_E];
-        st.E3 = a[P_E3];
-        st.U_int = st.E2 + st.E3;
-        for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
-        for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
-        st.U_ref = b[P_UREF] + (d.mode == MODE_UF ? a[P_UUF] : 0.0);
-        for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
-        st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
-        for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
-        st.V = st.box[0] * st.box[1] * st.box[2];
-        if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
-            st.err |= ERR_NONFINITE;
-        if (p.out) {
-            // dE/dstrain at diagonal strain e: Xi' (I + e)^-T
-            const double gsc = p.grad_scale ? p.grad_scale[s] : 1.0;
-            double *o = p.out + (int64_t)s * 20;
-            o[0] = st.U_int;
-            o[1] = st.U_ref;
-            for (int u = 0; u < 3; ++u)
-                for (int w = 0; w < 3; ++w) o[2 + 3 * u + w] = st.vir[3 * u + w] / st.pscale[w] * gsc;
-            for (int m = 0; m < 9; ++m) o[11 + m] = st.dth[m] * gsc;
-        }
-        if (step_end) {
-            baro_half(d, st, c.dt);  // step 9
-            st.step += 1;
-            st.k += 1;
-            st.remaining -= 1;
-            remaining = st.remaining;
-            if (c.log_every > 0 && c.log_cap > 0 && (st.step % c.log_every) == 0) {
-                const int64_t row = ((st.step / c.log_every) * c.n_sys + s) % c.log_cap;
-                double *L = p.log + row * 8;
-                L[0] = (double)st.step;
-                L[1] = st.lam;
-                L[2] = st.Ps * kGpaPerEvA3;
-                L[3] = st.lam != 0.0 ? st.Ps / st.lam * kGpaPerEvA3 : 0.0;
-                L[4] = 2.0 * st.K / (d.nf * 8.617333262e-5);
-                L[5] = st.U_int / (double)d.n;
-                L[6] = st.V / (double)d.n;
-                L[7] = st.W;
+    if (threadIdx.x == 0) {
+        const bool step_end = c.in_step != 0;
+        int64_t remaining = 0;
+        for (int q = 0; q < nq; ++q) {
+            const int s = sid[q];
+            const SysDesc &d = sdesc[q];
+            SysState &st = sst[q];
+            const double *a = sums[q], *b = sums[q] + kNumPart;
+            st.E2 = a[P_E];
+            st.E3 = a[P_E3];
+            st.U_int = st.E2 + st.E3;
+            for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
+            for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
+            st.U_ref = b[P_UREF] + (d.mode == MODE_UF ? a[P_UUF] : 0.0);
+            for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
+            st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
+            for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
+            st.V = st.box[0] * st.box[1] * st.box[2];
+            if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
+                st.err |= ERR_NONFINITE;
+            if (p.out) {
+                // dE/dstrain at diagonal strain e: Xi' (I + e)^-T
+                const double gsc = p.grad_scale ? p.grad_scale[s] : 1.0;
+                double *o = p.out + (int64_t)s * 20;
+                o[0] = st.U_int;
+                o[1] = st.U_ref;
+                for (int u = 0; u < 3; ++u)
+                    for (int w = 0; w < 3; ++w) o[2 + 3 * u + w] = st.vir[3 * u + w] / st.pscale[w] * gsc;
+                for (int m = 0; m < 9; ++m) o[11 + m] = st.dth[m] * gsc;
+            }
+            if (step_end) {
+                baro_half(d, st, c.dt);  // step 9
+                st.step += 1;
+                st.k += 1;
+                st.remaining -= 1;
+                remaining = st.remaining;
+                if (c.log_every > 0 && c.log_cap > 0 && (st.step % c.log_every) == 0) {
+                    const int64_t row = ((st.step / c.log_every) * c.n_sys + s) % c.log_cap;
+                    double *L = p.log + row * 8;
+                    L[0] = (double)st.step;
+                    L[1] = st.lam;
+                    L[2] = st.Ps * kGpaPerEvA3;
+                    L[3] = st.lam != 0.0 ? st.Ps / st.lam * kGpaPerEvA3 : 0.0;
+                    L[4] = 2.0 * st.K / (d.nf * 8.617333262e-5);
+                    L[5] = st.U_int / (double)d.n;
+                    L[6] = st.V / (double)d.n;
+                    L[7] = st.W;
+                }
             }
         }
+        if (step_end && remaining > 0)
+            group_start_step(c, sw, sdesc[0], sst[0], nq == 2 ? &sdesc[1] : nullptr, nq == 2 ? &sst[1] : nullptr);
     }
-    if (step_end && remaining > 0) group_start_step(c, p, sw, G);
+    __syncthreads();
+    for (int q = 0; q < nq; ++q) block_copy(&p.state[sid[q]], &sst[q], sizeof(SysState));
 }
 
 template <typename R, bool GRAD>
@@ -1347,7 +1368,9 @@ __global__ void k_begin_step(Ctl c, DevPtrs p, SwParams sw, int64_t n_steps)
     const Group G = p.groups[g];
     p.state[G.s0].remaining = n_steps;
     if (G.s1 >= 0) p.state[G.s1].remaining = n_steps;
-    group_start_step(c, p, sw, G);
+    const bool pair = G.s1 >= 0;
+    group_start_step(c, sw, p.desc[G.s0], p.state[G.s0], pair ? &p.desc[G.s1] : nullptr,
+                     pair ? &p.state[G.s1] : nullptr);
 }
 
 // Reset of every system's schedule state (lambda, P_S, work, schedule step)

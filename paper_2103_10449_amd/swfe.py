@@ -316,9 +316,9 @@ class Engine:
 
     def profile_steps(self, n_steps: int) -> dict:
         """Per-kernel HIP-event durations (ms, summed over n_steps eager steps)."""
-        ms = np.zeros(len(KERNEL_NAMES))
+        ms = np.zeros(16)
         self._check(self.lib.swfe_profile_steps(self.ctx, int(n_steps), _dp(ms), self._stream()))
-        return dict(zip(KERNEL_NAMES, ms))
+        return dict(zip(KERNEL_NAMES, ms[:len(KERNEL_NAMES)]))
 
     def neighbor_stats(self):
         """(ordered pairs within the cutoff, max per atom, Verlet-list entries)."""

@@ -70,6 +70,33 @@ def test_invalid_descriptors_rejected(swfe, sw_params):
     # reversible scaling needs positive lambda
     e = inputs.SystemSpec(mode=inputs.MODE_RS, sched_start=1.0, sched_end=0.0, T0=400, **base)
     assert _bytes(swfe, [e], sw_params)[0] == swfe.E_INVALID_ARG
+    # unknown mode and barostat kind
+    f = inputs.SystemSpec(mode=9, **base)
+    assert _bytes(swfe, [f], sw_params)[0] == swfe.E_INVALID_ARG
+    g = inputs.SystemSpec(mode=inputs.MODE_NVT, T0=400, baro=2, **base)
+    assert _bytes(swfe, [g], sw_params)[0] == swfe.E_INVALID_ARG
+    # the UF reference switches at fixed volume, with positive parameters
+    h = inputs.SystemSpec(mode=inputs.MODE_UF, T0=1000, p_damp=1.0, uf_p=25.0, uf_sigma=2.0, uf_T=1000.0,
+                          uf_rcut=5.0, **base)
+    assert _bytes(swfe, [h], sw_params)[0] == swfe.E_INVALID_ARG
+    u = inputs.SystemSpec(mode=inputs.MODE_UF, T0=1000, uf_p=0.0, **base)
+    assert _bytes(swfe, [u], sw_params)[0] == swfe.E_INVALID_ARG
+
+
+def test_degenerate_sizes_rejected(swfe, sw_params):
+    """No systems, a one-atom system, and systems that are not contiguous."""
+    x, box = inputs.diamond((2, 2, 2), 5.431)
+    sw = swfe.sw_params_struct(sw_params)
+    n = ctypes.c_size_t(0)
+    lib = swfe.load_library()
+    one = inputs.SystemSpec(x=x, v=np.zeros_like(x), box=box, mode=inputs.MODE_FORCE)
+    assert lib.swfe_workspace_bytes(swfe.system_descs([one]), 0, ctypes.byref(sw), ctypes.byref(n)) \
+        == swfe.E_INVALID_ARG
+    single = inputs.SystemSpec(x=x[:1], v=np.zeros_like(x[:1]), box=box, mode=inputs.MODE_FORCE)
+    assert _bytes(swfe, [single], sw_params)[0] == swfe.E_INVALID_ARG
+    desc = swfe.system_descs([one, one])
+    desc[1].offset = 3
+    assert lib.swfe_workspace_bytes(desc, 2, ctypes.byref(sw), ctypes.byref(n)) == swfe.E_INVALID_ARG
 
 
 def test_calls_before_init_fail_cleanly(swfe):
