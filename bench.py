@@ -44,10 +44,10 @@ SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
 # reads half the copied bytes (factor 2.000), WRITE_SIZE all of them (1.000).
 # The figures hold only for the kernel sources they were taken on (digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "086e1941f4340d2a881261c051f611e2f79319a847247412ac7a4d952d0ec66c",
+    "sources_sha256": "a0216a3dceb2f9cafe582b71723ceedd0412b76b63e81ab668e88b4517c55547",
     "skin": 1.4, "replicas": 64, "precision": "mixed",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "kib": {"pass1": (32565.4, 45736.5), "pass2": (31094.0, 23321.8)},  # (FETCH_SIZE, WRITE_SIZE)
+    "kib": {"pass1": (32234.6, 46449.1), "pass2": (31260.8, 23351.4)},  # (FETCH_SIZE, WRITE_SIZE)
 }
 
 
@@ -144,6 +144,55 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
                 n_rep=len(specs))
 
 
+def per_config_rates(P, seed, steps=200):
+    """Atom-steps/s of the smaller single-workload configurations (mixed and
+    FP64), each alone on the GPU: the 64-atom Frenkel-Ladd crystal, the
+    8000-atom diamond and liquid reversible-scaling runs, the dCCI pair of
+    4096-atom diamond and 8000-atom beta-tin; and force evaluations per
+    second (with the forced list build) of the 32768-atom crystal.  Small
+    systems are bound by the launch sequence, not by the atoms."""
+    import torch
+    from paper_2103_10449_amd import inputs, swfe
+    out = {}
+    cases = [("c1_diamond64_fl", lambda: inputs.config1()),
+             ("c2_diamond8000_rs", lambda: inputs.config2("diamond", steps=steps)),
+             ("c2_liquid8000_rs", lambda: inputs.config2("liquid", steps=steps)),
+             ("c3_dcci_diamond4096_betasn8000", lambda: inputs.config3(steps=steps))]
+    for name, mk in cases:
+        wl = mk()
+        row = {"atoms": wl.n_atoms}
+        for prec in ("mixed", "fp64"):
+            eng = swfe.Engine(copy.deepcopy(wl.systems), P, dt=wl.dt, seed=seed, precision=prec)
+            eng.set_skin(1.0)
+            eng.step(20, use_graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.step(steps, use_graph=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            eng.state()
+            eng.close()
+            row[prec] = wl.n_atoms * steps / dt
+        out[name] = row
+        print(f"# per-config {name}: {row}", file=sys.stderr, flush=True)
+    wl = inputs.config5()
+    row = {"atoms": wl.n_atoms, "unit": "atom force evaluations/s (forced list build)"}
+    for prec in ("mixed", "fp64"):
+        eng = swfe.Engine(copy.deepcopy(wl.systems), P, dt=wl.dt, seed=seed, precision=prec)
+        for grad in (False, True):
+            eng.compute_forces(param_grad=grad)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                eng.compute_forces(param_grad=grad)
+            torch.cuda.synchronize()
+            row[prec + ("_param_grad" if grad else "")] = wl.n_atoms * 20 / (time.perf_counter() - t0)
+        eng.close()
+    out["c5_diamond32768_forces"] = row
+    print(f"# per-config c5: {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def _oracle_systems(specs):
     from oracle import oracle as orc
     return [orc.OSystem(x=s.x, v=s.v, box=s.box, mode=s.mode, x0=s.x0, partner=s.partner,
@@ -212,6 +261,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-per-config", action="store_true",
+                    help="skip the per-configuration rates of the smaller workloads")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--skin", type=float, default=0.0,
                     help="fixed Verlet skin in A (default: chosen by timing during warm-up)")
@@ -311,6 +362,8 @@ def main():
                                     "per_kernel_us": {k: 1e3 * v / n_prof for k, v in p64.items()}}
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if not args.no_per_config:
+        out["per_config"] = per_config_rates(P, seed)
     print(json.dumps(out))
 
 
