@@ -330,6 +330,8 @@ Ctl make_ctl(const swfe_ctx *c, int in_step, int flags, int force_rebuild)
     k.seed = c->seed;
     k.flags = flags;
     k.list_cap = c->plan.list_cap;
+    k.list16 = 1;
+    for (const SysDesc &d : c->plan.desc) k.list16 &= d.n <= 65536 ? 1 : 0;
     k.has_uf = 0;
     for (const SysDesc &d : c->plan.desc) k.has_uf |= d.mode == MODE_UF ? 1 : 0;
     k.in_step = in_step;

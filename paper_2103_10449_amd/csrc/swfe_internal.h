@@ -104,7 +104,8 @@ struct Ctl {
     double dt;
     uint64_t seed;
     int32_t flags;          // PARAM_GRAD / STRAIN
-    int32_t list_cap;       // Verlet-list capacity per atom (rows of nl)
+    int32_t list_cap;       // Verlet-list capacity per atom (entries)
+    int32_t list16;         // 1: 16-bit list entries (every system below 65537 atoms)
     int32_t has_uf;         // 1: some system switches to the UF reference
     int32_t in_step;        // 1: the pass belongs to a dynamics step
     int32_t force_rebuild;  // 1: rebuild every system's list now
@@ -123,7 +124,7 @@ struct DevPtrs {
     float4 *xf;                           // FP32 positions wrapped into the box (list filter)
     int32_t *perm, *tperm, *norder, *rank, *cellid;  // norder: staged cell index
     int32_t *cell_count, *cell_start;
-    int32_t *nl, *nl_cnt;                 // Verlet list [kMaxList][n_total] of sorted positions
+    int32_t *nl, *nl_cnt;                 // Verlet list of sorted positions (layouts at list_put)
     int32_t *nnb;                         // neighbours within rc per atom (last pass 1)
     int32_t *sl;                          // [kMaxShort][n_total] those neighbours (sorted positions)
     void *mom;                            // [n_total][9] moments (v, M) in term precision

@@ -546,6 +546,54 @@ __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
     }
 }
 
+// Verlet-list storage.  With 32-bit entries, entry k of sorted atom s is the
+// sorted position of the neighbour at nl[k * N + s].  With 16-bit entries
+// (every system below 65537 atoms) it is the position relative to the
+// system's first atom, two entries per 32-bit word: halfword k & 1 of word
+// (k / 2) * N + s.  In both forms a row is contiguous over the atoms, so a
+// wavefront's list loads are coalesced; the 16-bit form halves their
+// number and their bytes.
+__device__ __forceinline__ void list_put(const Ctl &c, int32_t *nl, int k, int64_t N, int s, int j, int off)
+{
+    if (c.list16)
+        reinterpret_cast<uint16_t *>(nl)[((int64_t)(k >> 1) * N + s) * 2 + (k & 1)] = (uint16_t)(j - off);
+    else
+        nl[(int64_t)k * N + s] = j;
+}
+
+// Entries k0 .. k0 + B - 1 (k0 and B even) of atom t's Verlet list of cnt >= 1
+// entries.  Words past the end re-read the last valid one (no branch around
+// the load) and entries past the end yield t itself, whose position is always
+// valid to load.
+template <int B>
+__device__ __forceinline__ void list_batch(const Ctl &c, const int32_t *nl, int k0, int cnt, int64_t N, int t,
+                                           int off, int (&jb)[B])
+{
+    static_assert(B % 2 == 0, "pairs of entries");
+    if (c.list16) {
+        const uint32_t *w32 = reinterpret_cast<const uint32_t *>(nl);
+        const int last = (cnt - 1) >> 1;
+        uint32_t w[B / 2];
+#pragma unroll
+        for (int u = 0; u < B / 2; ++u) {
+            const int pr = (k0 >> 1) + u;
+            w[u] = w32[(int64_t)(pr < last ? pr : last) * N + t];
+        }
+#pragma unroll
+        for (int u = 0; u < B / 2; ++u) {
+            jb[2 * u] = k0 + 2 * u < cnt ? off + (int)(w[u] & 0xffffu) : t;
+            jb[2 * u + 1] = k0 + 2 * u + 1 < cnt ? off + (int)(w[u] >> 16) : t;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int k = k0 + u < cnt ? k0 + u : cnt - 1;
+            const int j = nl[(int64_t)k * N + t];
+            jb[u] = k0 + u < cnt ? j : t;
+        }
+    }
+}
+
 // Verlet list of sorted positions within rc + skin from the (up to) 27 cells
 // around the atom's cell (fewer when a dimension has fewer than 3 cells, so
 // that no cell is visited twice).  32 lanes per atom, one per stencil cell:
@@ -621,7 +669,7 @@ __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const
         while (m) {
             const int k = __ffsll((long long)m) - 1;
             m &= m - 1;
-            if (slot < c.list_cap) p.nl[(int64_t)slot * N + s] = j0 + k;
+            if (slot < c.list_cap) list_put(c, p.nl, slot, N, s, j0 + k, (int)d.off);
             ++slot;
         }
     }
@@ -722,6 +770,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const int t = tile.start + threadIdx.x;
         const double4 xi = p.xs[t];
         const int cnt = p.nl_cnt[t];
+        const int off = (int)p.desc[sys].off;
         // Filter: the list candidates now within rc go to the short list.
         // It is cheap per candidate, so lanes whose candidates are mostly
         // outside rc do not hold the wave in the term evaluation below.
@@ -740,8 +789,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             // their positions, are in flight together
             for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
                 int jb[kBatchA];
-#pragma unroll
-                for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
+                list_batch<kBatchA>(c, p.nl, k0, cnt, N, t, off, jb);
                 float4 xj[kBatchA];
 #pragma unroll
                 for (int u = 0; u < kBatchA; ++u) xj[u] = p.xf[jb[u]];
@@ -900,8 +948,7 @@ __global__ void __launch_bounds__(256) k_uf(Ctl c, DevPtrs p)
         double fx = 0, fy = 0, fz = 0;
         for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
             int jb[kBatchA];
-#pragma unroll
-            for (int u = 0; u < kBatchA; ++u) jb[u] = list_entry(p.nl, k0 + u, cnt, N, t);
+            list_batch<kBatchA>(c, p.nl, k0, cnt, N, t, (int)d.off, jb);
             double4 xj[kBatchA];
 #pragma unroll
             for (int u = 0; u < kBatchA; ++u) xj[u] = p.xs[jb[u]];

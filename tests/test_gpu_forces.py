@@ -137,6 +137,35 @@ def test_full_size_diamond32768_sampled(swfe, sw_params):
         eng.close()
 
 
+@pytest.mark.parametrize("prec,ftol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_system_above_16bit_list_indices(swfe, sw_params, prec, ftol):
+    """A system of more than 65536 atoms switches the Verlet list of the whole
+    batch to 32-bit entries.  The system is a 6144-atom perturbed diamond
+    block (16 x 16 x 3 cells) repeated 11 times along z (67584 atoms), so
+    every copy of an atom feels the forces of the small periodic block, which
+    the oracle evaluates; a 64-atom crystal in the same batch must come out
+    bitwise as it does alone (16-bit lists: same entries in the same order)."""
+    xl, box = inputs.diamond((16, 16, 3), 5.431)
+    x = inputs.perturb(xl, 0.15, inputs.rng(704, 0, 0))
+    big_x = np.concatenate([x + np.array([0.0, 0.0, k * box[2]]) for k in range(11)])
+    big = spec(big_x, [box[0], box[1], 11 * box[2]])
+    small = diamond_spec(2, 5)
+    small.mode = inputs.MODE_FORCE
+    print(f"big N={big.n} prec {prec}", flush=True)
+    ref = orc.sw_eval(x, box, sw_params)
+    eng = swfe.Engine([small, big], sw_params, precision=prec)
+    out = eng.compute_forces().cpu().numpy()
+    Fb = eng.forces(1)
+    assert force_err(Fb, np.tile(ref["F"], (11, 1))) < ftol
+    assert out[1, 0] / big.n == pytest.approx(ref["E"] / len(x), abs=1e-12 if prec == "fp64" else 1e-5)
+    Fs = eng.forces(0)
+    eng.close()
+    alone = swfe.Engine([small], sw_params, precision=prec)
+    alone.compute_forces()
+    assert np.array_equal(Fs, alone.forces(0))
+    alone.close()
+
+
 def test_neighbour_overflow_is_reported(swfe, sw_params):
     """More than 32 atoms within the cutoff of an atom: the kernel caps the
     list and the library reports SWFE_E_OVERFLOW."""
