@@ -90,7 +90,7 @@ struct SysState {
     int64_t remaining;              // steps left in the current call
     int64_t n_rebuild;              // Verlet-list rebuilds so far
     int32_t err;
-    int32_t rb;                     // 1: the list is rebuilt in this step
+    int32_t pad;
 };
 
 struct Tile {

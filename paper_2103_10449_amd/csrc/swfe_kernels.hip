@@ -44,21 +44,6 @@
 namespace swfe {
 
 // ------------------------------------------------------------------ utils --
-__device__ __forceinline__ int ld_coherent(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void st_coherent(int32_t *p, int v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double ldd_coherent(const double *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Blocks are dispatched round robin over the 8 XCDs; block b runs tile
 // (b % 8) * stride + b / 8, so each XCD works on a contiguous run of tiles
 // (neighbouring cells) and keeps their data in its own L2.  -1: no tile.
@@ -454,7 +439,6 @@ __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwPa
     __shared__ int rb_s, at_s;
     if (tid == 0) {
         const bool rb = list_stale(c, p, sw, sys);
-        st.rb = rb ? 1 : 0;
         // clear the slot the next step's integrate fills (both on a forced build)
         p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
         if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
