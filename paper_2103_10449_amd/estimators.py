@@ -7,7 +7,10 @@ from typing import Sequence, Tuple
 
 import numpy as np
 
-KB = 8.617333262e-5  # eV/K
+KB = 8.617333262e-5            # eV/K
+HBAR = 6.582119569e-4          # eV ps
+AMU_A2_PS2 = 1.0364269656e-4   # eV per amu A^2 / ps^2
+EV_A3_PER_GPA = 1.0 / 160.21766208  # eV/A^3 per GPa
 
 
 def delta_f(w_forward, w_backward) -> float:
@@ -67,6 +70,54 @@ def einstein_free_energy_difference(k1: float, k2: float, T: float, n_atoms: int
     """F(k2) - F(k1) of a classical Einstein crystal of n_atoms 3D oscillators
     at temperature T: (3 n / 2) kB T ln(k2 / k1)."""
     return 1.5 * n_atoms * KB * T * np.log(k2 / k1)
+
+
+def einstein_free_energy(n_atoms: int, k: float, T: float, mass: float) -> float:
+    """Helmholtz free energy (eV) of n_atoms independent classical 3D
+    oscillators of spring k (eV/A^2) and mass (amu) at T:
+    3 N kB T ln(hbar omega / kB T), omega = sqrt(k / m)."""
+    omega = np.sqrt(k / (mass * AMU_A2_PS2))  # 1/ps
+    kT = KB * T
+    return 3.0 * n_atoms * kT * np.log(HBAR * omega / kT)
+
+
+def com_correction(n_atoms: int, k: float, T: float, volume: float) -> float:
+    """Free energy (eV) that turns the Einstein reference of a run whose
+    centre of mass is held fixed into the free crystal's:
+    kB T ln[(N / V) (2 pi kB T / (N k))^(3/2)].
+
+    Derivation (classical, atoms on their sites): holding the centre of mass
+    R at the anchors' centre and the total momentum P at zero, the Einstein
+    crystal's integrals over the N positions and momenta reduce to 3(N - 1)
+    oscillators times N^(3/2) (positions, from delta(sum u / N)) and
+    N^(-3/2) (momenta, from delta(sum p)); a translation-invariant crystal
+    recovers its free integrals as (V / N) (2 pi N m kB T)^(3/2) times its
+    constrained ones: R ranges over the volume per lattice translation (a
+    translation by a lattice vector is a relabelling of the sites, which the
+    crystal's basin already counts) and P is Gaussian with mass N m.  With
+    the switching run's free-energy difference taken in the constrained
+    ensemble, F_crystal = F_Einstein(N) + this term + F_SW,c - F_E,c.
+    hbar and m cancel between the two pieces."""
+    kT = KB * T
+    return kT * np.log((n_atoms / volume) * (2.0 * np.pi * kT / (n_atoms * k)) ** 1.5)
+
+
+def solid_free_energy(n_atoms: int, k: float, T: float, mass: float, volume: float,
+                      w_to_einstein, w_from_einstein) -> float:
+    """Absolute Helmholtz free energy (eV) of a crystal at (V, T) by
+    Frenkel-Ladd switching (section 2.1): the Einstein reference (with the
+    centre-of-mass term) minus F(Einstein) - F(crystal) = (mean W(crystal ->
+    Einstein) - mean W(Einstein -> crystal)) / 2 (eq. dF), from runs whose
+    centre of mass is fixed."""
+    return (einstein_free_energy(n_atoms, k, T, mass) + com_correction(n_atoms, k, T, volume)
+            - delta_f(w_to_einstein, w_from_einstein))
+
+
+def coexistence_pressure(P: float, g1: float, v1: float, g2: float, v2: float) -> float:
+    """Pressure (GPa) where two phases with per-atom Gibbs energies g1, g2 (eV)
+    and volumes v1, v2 (A^3) at pressure P (GPa) have equal g, to first order
+    in the pressure: g_i(P') = g_i + v_i (P' - P)."""
+    return P + (g2 - g1) / ((v1 - v2) * EV_A3_PER_GPA)
 
 
 def dcci_coexistence(T0: float, lam: Sequence[float], Ps: Sequence[float]) -> Tuple[np.ndarray, np.ndarray]:

@@ -82,3 +82,56 @@ def test_dcci_coexistence_scaling():
     T, P = est.dcci_coexistence(1000.0, [1.0, 2.0, 0.5], [3.0, 3.0, 1.0])
     np.testing.assert_allclose(T, [1000.0, 500.0, 2000.0])
     np.testing.assert_allclose(P, [3.0, 1.5, 2.0])
+
+
+def _constrained_integrals_1d(n, a, b, h=2e-3, L=8.0):
+    """Brute-force quadrature of the centre-of-mass-constrained integrals of
+    n 1D oscillators: int du delta(sum u / n) exp(-a sum u^2) and
+    int dp delta(sum p) exp(-b sum p^2), by eliminating the last coordinate
+    on a grid (n = 2: 1D grid, n = 3: 2D grid)."""
+    su = np.arange(-L, L + h / 2, h) / np.sqrt(a)
+    sp = np.arange(-L, L + h / 2, h) / np.sqrt(b)
+    if n == 2:
+        zu = n * np.trapezoid(np.exp(-a * (su ** 2 + su ** 2)), su)
+        zp = np.trapezoid(np.exp(-b * (sp ** 2 + sp ** 2)), sp)
+    else:
+        U1, U2 = np.meshgrid(su[::8], su[::8], indexing="ij")
+        zu = n * np.trapezoid(np.trapezoid(np.exp(-a * (U1 ** 2 + U2 ** 2 + (U1 + U2) ** 2)), su[::8]), su[::8])
+        P1, P2 = np.meshgrid(sp[::8], sp[::8], indexing="ij")
+        zp = np.trapezoid(np.trapezoid(np.exp(-b * (P1 ** 2 + P2 ** 2 + (P1 + P2) ** 2)), sp[::8]), sp[::8])
+    return zu, zp
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_einstein_reference_with_fixed_centre_of_mass_brute_force(n):
+    """The absolute Einstein reference (Einstein free energy plus the
+    centre-of-mass term) equals -kT ln of the free crystal's integral built
+    from brute-force quadratures of the constrained ones: (V / N) (2 pi N m
+    kT)^(3/2) Z_pos Z_mom / h^(3N), Z_pos and Z_mom the cubes of the 1D
+    constrained position and momentum integrals.  A wrong oscillator count
+    (3N instead of 3(N - 1)) or a dropped N^(3/2) fails by kT ln N or more."""
+    k, T, mass, V = 6.0, 500.0, 28.0855, 173.0
+    kT = KB * T
+    m = mass * est.AMU_A2_PS2                  # eV ps^2 / A^2
+    zu, zp = _constrained_integrals_1d(n, k / (2 * kT), 1 / (2 * m * kT))
+    h = 2 * np.pi * est.HBAR
+    lnZ = np.log(V / n) + 1.5 * np.log(2 * np.pi * n * m * kT) + 3 * np.log(zu) + 3 * np.log(zp) - 3 * n * np.log(h)
+    F = est.einstein_free_energy(n, k, T, mass) + est.com_correction(n, k, T, V)
+    assert F == pytest.approx(-kT * lnZ, abs=1e-9)
+    # and the closed forms of the two constrained integrals
+    assert zu == pytest.approx(np.sqrt(n) * (np.pi / (k / (2 * kT))) ** ((n - 1) / 2), rel=1e-9)
+    assert zp == pytest.approx((np.pi * 2 * m * kT) ** ((n - 1) / 2) / np.sqrt(n), rel=1e-9)
+
+
+def test_solid_free_energy_and_coexistence_pressure():
+    """F = Einstein reference - dF(crystal -> Einstein); two phases with
+    linear g(P) cross where the first-order estimate says."""
+    N, k, T, m, V = 512, 7.0, 400.0, 28.0855, 512 * 20.0
+    ref = est.einstein_free_energy(N, k, T, m) + est.com_correction(N, k, T, V)
+    wf, wb = np.array([3.0, 3.2]), np.array([-2.0, -2.2])
+    assert est.solid_free_energy(N, k, T, m, V, wf, wb) == pytest.approx(ref - 0.5 * (3.1 + 2.1))
+    g1, v1, g2, v2, P = -4.30, 19.0, -4.31, 16.0, 13.0
+    Pc = est.coexistence_pressure(P, g1, v1, g2, v2)
+    c = est.EV_A3_PER_GPA
+    assert g1 + v1 * (Pc - P) * c == pytest.approx(g2 + v2 * (Pc - P) * c, abs=1e-14)
+    assert Pc < P  # the denser phase 2 is lower in g at P, so the crossing is below P
