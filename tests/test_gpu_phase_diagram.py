@@ -18,7 +18,9 @@ paper does not give (equilibration length, barostat parameters).  Measured:
 the melting lines cross at (1210.3 K, 9.93 GPa); the cd/beta-tin line
 passes 1210 K at 10.12 +- 0.02 GPa (six realisations, insensitive to the
 equilibration length and barostat period), 0.2 GPa above the paper's
-crossing."""
+crossing: this build's own absolute free energies put P_coex(400 K) at
+13.07 GPa, and an error d in the starting pressure reappears as d T / 400 K
+along the line (the line from 13.07 GPa passes 1210 K at 9.86 GPa)."""
 import numpy as np
 import pytest
 
