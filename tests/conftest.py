@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
-    config.addinivalue_line("markers", "slow: long statistical CPU test")
+    config.addinivalue_line("markers", "slow: long statistical or end-to-end test")
 
 
 @pytest.fixture(scope="session")
