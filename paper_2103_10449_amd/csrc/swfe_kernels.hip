@@ -1247,6 +1247,20 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
     for (int q = 0; q < nq; ++q) block_copy(&p.state[sid[q]], &sst[q], sizeof(SysState));
 }
 
+// Normals of atom t's next O step: stored in zs and added to the tile's
+// noise sums.
+template <int NV>
+__device__ __forceinline__ void next_normals(const Ctl &c, const SysDesc &d, const SysState &st, int t, int atom,
+                                             double4 *zs, double (&acc)[NV])
+{
+    double z[3];
+    normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)atom, z);
+    zs[t] = make_double4(z[0], z[1], z[2], 0.0);
+    acc[P_NOISE] = z[0];
+    acc[P_NOISE + 1] = z[1];
+    acc[P_NOISE + 2] = z[2];
+}
+
 template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass2(Ctl c, DevPtrs p, SwParams sw)
 {
@@ -1274,6 +1288,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const double4 v0 = p.vs[t];
         const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
         const int atom = p.perm[t] - d.off;
+        // normals of the next O step (stored for it, and summed for its
+        // zero-sum correction), drawn while the operands above load; the
+        // gradient variant draws them at the end, where registers are free
+        if (!GRAD && o_step_on(d)) next_normals(c, d, st, t, atom, p.zs, acc);
         const R rc = (R)sw.rc, gsig = (R)(sw.gam * sw.sig), c0 = (R)sw.cos0, hle = (R)(0.5 * sw.le);
         double F3x = 0, F3y = 0, F3z = 0;
         double vxx = 0, vyy = 0, vzz = 0, vxy = 0, vxz = 0, vyz = 0;
@@ -1369,16 +1387,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         acc[P_K] = d.mvv2e_m * (v.x * v.x);
         acc[P_K + 1] = d.mvv2e_m * (v.y * v.y);
         acc[P_K + 2] = d.mvv2e_m * (v.z * v.z);
-        // normals of the next O step: stored for it, and summed for its
-        // zero-sum correction
-        if (o_step_on(d)) {
-            double z[3];
-            normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)atom, z);
-            p.zs[t] = make_double4(z[0], z[1], z[2], 0.0);
-            acc[P_NOISE] = z[0];
-            acc[P_NOISE + 1] = z[1];
-            acc[P_NOISE + 2] = z[2];
-        }
+        if (GRAD && o_step_on(d)) next_normals(c, d, st, t, atom, p.zs, acc);
     }
     block_reduce<NV>(acc, p.part2 + (int64_t)ti * kNumPart);
 }
