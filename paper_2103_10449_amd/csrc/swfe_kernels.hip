@@ -545,24 +545,42 @@ __device__ __forceinline__ void list_put(const Ctl &c, int32_t *nl, int k, int64
         nl[(int64_t)k * N + s] = j;
 }
 
-// Entries k0 .. k0 + B - 1 (k0 and B even) of atom t's Verlet list of cnt >= 1
-// entries.  Words past the end re-read the last valid one (no branch around
-// the load) and entries past the end yield t itself, whose position is always
-// valid to load.
+// Raw words holding entries k0 .. k0 + B - 1 (k0 and B even) of atom t's
+// Verlet list: B / 2 words in the 16-bit form, B in the 32-bit form.  Rows
+// at or past `rows` re-read row rows - 1 (no branch around the load); with
+// rows = list_cap the addresses do not depend on the atom's entry count, so
+// the first batch can load together with that count.
 template <int B>
-__device__ __forceinline__ void list_batch(const Ctl &c, const int32_t *nl, int k0, int cnt, int64_t N, int t,
-                                           int off, int (&jb)[B])
+__device__ __forceinline__ void list_load(const Ctl &c, const int32_t *nl, int k0, int rows, int64_t N, int t,
+                                          uint32_t (&w)[B])
 {
     static_assert(B % 2 == 0, "pairs of entries");
+    const uint32_t *w32 = reinterpret_cast<const uint32_t *>(nl);
     if (c.list16) {
-        const uint32_t *w32 = reinterpret_cast<const uint32_t *>(nl);
-        const int last = (cnt - 1) >> 1;
-        uint32_t w[B / 2];
+        const int last = (rows - 1) >> 1;
 #pragma unroll
         for (int u = 0; u < B / 2; ++u) {
             const int pr = (k0 >> 1) + u;
             w[u] = w32[(int64_t)(pr < last ? pr : last) * N + t];
         }
+#pragma unroll
+        for (int u = B / 2; u < B; ++u) w[u] = 0u;
+    } else {
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int k = k0 + u < rows ? k0 + u : rows - 1;
+            w[u] = w32[(int64_t)k * N + t];
+        }
+    }
+}
+
+// Sorted positions of entries k0 .. k0 + B - 1 from their raw words; entries
+// at or past cnt yield t itself, whose position is always valid to load.
+template <int B>
+__device__ __forceinline__ void list_decode(const Ctl &c, const uint32_t (&w)[B], int k0, int cnt, int t, int off,
+                                            int (&jb)[B])
+{
+    if (c.list16) {
 #pragma unroll
         for (int u = 0; u < B / 2; ++u) {
             jb[2 * u] = k0 + 2 * u < cnt ? off + (int)(w[u] & 0xffffu) : t;
@@ -570,12 +588,18 @@ __device__ __forceinline__ void list_batch(const Ctl &c, const int32_t *nl, int 
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int k = k0 + u < cnt ? k0 + u : cnt - 1;
-            const int j = nl[(int64_t)k * N + t];
-            jb[u] = k0 + u < cnt ? j : t;
-        }
+        for (int u = 0; u < B; ++u) jb[u] = k0 + u < cnt ? (int)w[u] : t;
     }
+}
+
+// Entries k0 .. k0 + B - 1 of atom t's Verlet list of cnt >= 1 entries.
+template <int B>
+__device__ __forceinline__ void list_batch(const Ctl &c, const int32_t *nl, int k0, int cnt, int64_t N, int t,
+                                           int off, int (&jb)[B])
+{
+    uint32_t w[B];
+    list_load<B>(c, nl, k0, cnt, N, t, w);
+    list_decode<B>(c, w, k0, cnt, t, off, jb);
 }
 
 // Verlet list of sorted positions within rc + skin from the (up to) 27 cells
@@ -753,6 +777,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         eff_box(st, box, ibox);
         const int t = tile.start + threadIdx.x;
         const double4 xi = p.xs[t];
+        // the first batch of list words loads together with the count
+        uint32_t w0[kBatchA];
+        list_load<kBatchA>(c, p.nl, 0, c.list_cap, N, t, w0);
         const int cnt = p.nl_cnt[t];
         const int off = (int)p.desc[sys].off;
         // Filter: the list candidates now within rc go to the short list.
@@ -772,8 +799,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             // batches of kBatchA candidates: all their indices, then all
             // their positions, are in flight together
             for (int k0 = 0; k0 < cnt; k0 += kBatchA) {
+                uint32_t w[kBatchA];
+                if (k0 == 0) {
+#pragma unroll
+                    for (int u = 0; u < kBatchA; ++u) w[u] = w0[u];
+                } else {
+                    list_load<kBatchA>(c, p.nl, k0, cnt, N, t, w);
+                }
                 int jb[kBatchA];
-                list_batch<kBatchA>(c, p.nl, k0, cnt, N, t, off, jb);
+                list_decode<kBatchA>(c, w, k0, cnt, t, off, jb);
                 float4 xj[kBatchA];
 #pragma unroll
                 for (int u = 0; u < kBatchA; ++u) xj[u] = p.xf[jb[u]];
@@ -1287,6 +1321,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const double4 F2 = p.fs[t];
         const double4 v0 = p.vs[t];
         const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
+        // the first batch of short-list entries loads together with its count
+        constexpr int kBatch2 = Batch<R, GRAD>::P2;
+        int s0[kBatch2];
+#pragma unroll
+        for (int u = 0; u < kBatch2; ++u) s0[u] = p.sl[(int64_t)u * N + t];
+        const int cnt = p.nnb[t];
         const int atom = p.perm[t] - d.off;
         // normals of the next O step (stored for it, and summed for its
         // zero-sum correction), drawn while the operands above load; the
@@ -1298,12 +1338,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         double gg = 0, ga = 0, gs = 0;  // sum H g dln g/d(gamma, a, sigma)
         // the neighbours within rc that pass 1 found at these positions, in
         // batches whose indices, positions and moments are loaded together
-        const int cnt = p.nnb[t];
-        constexpr int kBatch2 = Batch<R, GRAD>::P2;
         for (int k0 = 0; k0 < cnt; k0 += kBatch2) {
             int jb[kBatch2];
+            if (k0 == 0) {
 #pragma unroll
-            for (int u = 0; u < kBatch2; ++u) jb[u] = list_entry(p.sl, k0 + u, cnt, N, t);
+                for (int u = 0; u < kBatch2; ++u) jb[u] = u < cnt ? s0[u] : t;
+            } else {
+#pragma unroll
+                for (int u = 0; u < kBatch2; ++u) jb[u] = list_entry(p.sl, k0 + u, cnt, N, t);
+            }
             double4 xjb[kBatch2];
             Mom<R> mjb[kBatch2];
 #pragma unroll
