@@ -17,8 +17,10 @@
 //                2 scatter: atom data into its cell's segment (staging)
 //                3 order:   in-cell order by the caller's atom index
 //                4 list:    Verlet list within rc + skin from the 27 cells
-//   pass1        filter of the Verlet list to the short list (within rc),
-//                then pair terms and the 11 three-body moments per atom
+//   pass1        filter of the Verlet list (16-bit entries relative to the
+//                system when every system has at most 65536 atoms) to the
+//                short list (within rc), then pair terms and the 11
+//                three-body moments per atom
 //   pass2        three-body force gather from own and neighbour moments,
 //                Einstein springs, final B kick, per-tile partial sums, the
 //                normals of the next O step (stored, and summed for its
@@ -748,7 +750,7 @@ struct Batch {
     static constexpr int P2 = sizeof(R) == 4 ? 4 : 2;
 };
 
-// Entry k of atom t's list ([row][n_total] layout, n valid rows, n >= 1).
+// Entry k of atom t's short list ([row][n_total] layout, n valid rows, n >= 1).
 // Rows past the end read the last valid row (no branch around the load) and
 // yield t itself, whose position is always valid to load.
 __device__ __forceinline__ int list_entry(const int32_t *list, int k, int n, int64_t N, int t)
