@@ -113,6 +113,37 @@ def solid_free_energy(n_atoms: int, k: float, T: float, mass: float, volume: flo
             - delta_f(w_to_einstein, w_from_einstein))
 
 
+def ideal_gas_free_energy(n_atoms: int, volume: float, T: float, mass: float) -> float:
+    """Helmholtz free energy (eV) of n_atoms classical ideal-gas atoms of mass
+    (amu) in volume (A^3) at T: -kB T ln(V^N / (N! Lambda^(3N))), Lambda =
+    h / sqrt(2 pi m kB T), with ln N! exact (lgamma)."""
+    from math import lgamma
+    kT = KB * T
+    lam = 2.0 * np.pi * HBAR / np.sqrt(2.0 * np.pi * mass * AMU_A2_PS2 * kT)  # A
+    return -kT * (n_atoms * np.log(volume) - lgamma(n_atoms + 1.0) - 3.0 * n_atoms * np.log(lam))
+
+
+def liquid_free_energy(n_atoms: int, volume: float, T: float, mass: float, w_gas_to_uf, w_uf_to_gas,
+                       w_liquid_to_uf, w_uf_to_liquid) -> float:
+    """Absolute Helmholtz free energy (eV) of a liquid at (V, T) through the
+    Uhlenbeck-Ford fluid (section 4.1): the ideal gas, plus F_UF - F_gas from
+    switching the UF pair potential on in the ideal gas, minus F_UF -
+    F_liquid from switching the liquid to the UF fluid, both at this volume
+    and temperature (eq. dF for each).  Both Hamiltonians along the way are
+    translation invariant, so holding the centre of mass fixed in the runs
+    changes neither difference."""
+    return (ideal_gas_free_energy(n_atoms, volume, T, mass) + delta_f(w_gas_to_uf, w_uf_to_gas)
+            - delta_f(w_liquid_to_uf, w_uf_to_liquid))
+
+
+def transition_temperature(T: float, g1: float, h1: float, g2: float, h2: float) -> float:
+    """Temperature where two phases with per-atom Gibbs energies g1, g2 and
+    enthalpies h1, h2 (eV) at T have equal g, taking the enthalpies constant
+    near T (Gibbs-Helmholtz: g / T changes by h d(1/T)): T / (1 - (g2 - g1) /
+    (h2 - h1))."""
+    return T / (1.0 - (g2 - g1) / (h2 - h1))
+
+
 def coexistence_pressure(P: float, g1: float, v1: float, g2: float, v2: float) -> float:
     """Pressure (GPa) where two phases with per-atom Gibbs energies g1, g2 (eV)
     and volumes v1, v2 (A^3) at pressure P (GPa) have equal g, to first order

@@ -135,3 +135,28 @@ def test_solid_free_energy_and_coexistence_pressure():
     c = est.EV_A3_PER_GPA
     assert g1 + v1 * (Pc - P) * c == pytest.approx(g2 + v2 * (Pc - P) * c, abs=1e-14)
     assert Pc < P  # the denser phase 2 is lower in g at P, so the crossing is below P
+
+
+def test_ideal_gas_entropy_is_sackur_tetrode_argon():
+    """S = -dF/dT of the ideal gas at fixed V for argon (39.948 amu) at
+    298.15 K and 1 bar: the tabulated standard molar entropy, 154.8 J/(mol
+    K), pins the thermal wavelength (hbar, the amu conversion, kB)."""
+    T, P_bar, m = 298.15, 1.0, 39.948
+    N = 10 ** 6
+    V = N * KB * T / (P_bar * 1e5 / 1.602176634e-19 * 1e-30)   # A^3
+    h = 1e-3
+    S = -(est.ideal_gas_free_energy(N, V, T + h, m) - est.ideal_gas_free_energy(N, V, T - h, m)) / (2 * h)
+    S_molar = S / N * 1.602176634e-19 * 6.02214076e23                 # J/(mol K)
+    assert S_molar == pytest.approx(154.8, abs=0.1)
+
+
+def test_transition_temperature_and_liquid_assembly():
+    """Phases with g_i(T') = h_i + (g_i(T) - h_i) T'/T (constant h, linear
+    entropy term) cross where the first-order estimate says; the liquid
+    assembly adds the two switching free energies with the right signs."""
+    T, g1, h1, g2, h2 = 1600.0, -4.10, -3.90, -4.08, -3.50
+    Tt = est.transition_temperature(T, g1, h1, g2, h2)
+    g = lambda gi, hi: hi + (gi - hi) * Tt / T
+    assert g(g1, h1) == pytest.approx(g(g2, h2), abs=1e-12)
+    F = est.liquid_free_energy(100, 2000.0, T, 28.0855, [1.0], [-0.8], [-3.0], [3.4])
+    assert F == pytest.approx(est.ideal_gas_free_energy(100, 2000.0, T, 28.0855) + 0.9 - (-3.2))

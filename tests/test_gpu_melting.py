@@ -1,0 +1,154 @@
+"""The melting temperature of Stillinger-Weber silicon at zero pressure from
+absolute free energies (section 2.1, section 4.1), the paper's T_m(0 GPa) =
+1689.2(3) K.
+
+Both phases at (1689.2 K, 0 GPa) after NPT equilibration:
+* diamond (4096 atoms): Frenkel-Ladd switching to its Einstein crystal at
+  its mean box, springs matched to the measured fluctuations;
+* liquid (3000 atoms): the SW liquid switched to the Uhlenbeck-Ford fluid
+  (p = 25, sigma = 2 A, cutoff 8 A) at its mean volume, and an ideal gas in
+  the same box switched on to the same UF fluid, so that F_liquid = F_gas +
+  (F_UF - F_gas) - (F_UF - F_liquid) with no tabulated UF free energy.
+The per-atom Gibbs energies (g = F / N at P = 0) and enthalpies (the mean
+potential energy per atom; the kinetic parts are equal) give the crossing
+temperature.  Four realisations of each phase, 100 ps per switching
+direction, mixed precision.
+
+Measured: T_m(0 GPa) = 1684.8 +- 1.9 K (paper 1689.2(3)); g(liquid) -
+g(cd) = -0.85 meV/atom at 1689.2 K, latent heat 0.323 eV/atom, liquid
+18.87 A^3/atom against 20.35 for the crystal; dissipated heat 0.05-0.4
+meV/atom (crystal) and about 3.5 meV/atom (liquid legs)."""
+import numpy as np
+import pytest
+
+from paper_2103_10449_amd import estimators as est
+from paper_2103_10449_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+T = 1689.2
+N_LIQ, REAL = 3000, 4
+N_EQ, N_AVG, N_HOLD, N_SW = 30000, 20000, 10000, 100000
+UF = dict(uf_p=inputs.UF_P, uf_sigma=inputs.UF_SIGMA, uf_T=T, uf_rcut=inputs.UF_RCUT)
+
+
+def _switch(eng, specs, n_hold, n_sw):
+    """Hold at lambda = 1, switch 1 -> 0, hold at 0, switch 0 -> 1; the work of
+    each switching leg per system."""
+    def leg(a, b, n):
+        for s in specs:
+            s.sched_start, s.sched_end, s.sched_steps = a, b, n
+        eng.set_schedule(specs)
+        eng.step(n if n else n_hold)
+        return eng.work_integral()["W"].copy()
+    leg(1.0, 1.0, 0)
+    wf = leg(1.0, 0.0, n_sw)
+    leg(0.0, 0.0, 0)
+    wb = leg(0.0, 1.0, n_sw)
+    return wf, wb
+
+
+@pytest.fixture(scope="module")
+def phases(sw_params):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_10449_amd import swfe
+    lat, b0 = inputs.diamond((8, 8, 8), 5.431)
+    npt = []
+    for r in range(REAL):
+        npt.append(inputs.SystemSpec(x=lat, v=inputs.maxwell(len(lat), T, inputs.rng(998, r, 1)), box=b0,
+                                     phase="cd", mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0,
+                                     pressure=0.0, stream=2 * r))
+        x, b = inputs.liquid_rsa(N_LIQ, inputs.rng(998, r, 2))
+        npt.append(inputs.SystemSpec(x=x, v=inputs.maxwell(N_LIQ, T, inputs.rng(998, r, 3)), box=b, phase="liq",
+                                     mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=0.0,
+                                     stream=2 * r + 1))
+    eng = swfe.Engine(npt, sw_params, dt=0.001, seed=21, precision="mixed")
+    eng.set_skin(1.0)
+    eng.step(N_EQ)
+    boxes = [[] for _ in npt]
+    u = [[] for _ in npt]
+    msd = [[] for _ in npt]
+    for _ in range(N_AVG // 1000):
+        eng.step(1000)
+        st = eng.state()
+        for q, s in enumerate(npt):
+            boxes[q].append(st[q]["box"])
+            u[q].append(st[q]["U_int"] / s.n)
+            if s.phase == "cd":
+                L = st[q]["box"]
+                d = eng.positions(q) - lat / b0 * L
+                d -= L * np.round(d / L)
+                d -= d.mean(axis=0)
+                msd[q].append(np.mean(np.sum(d * d, axis=1)))
+    st = eng.state()
+    assert not any(s["err"] for s in st)
+    sw_specs, gas_specs, info = [], [], []
+    for q, s in enumerate(npt):
+        L = np.mean(boxes[q], axis=0)
+        x = eng.positions(q) * (L / st[q]["box"])
+        V = float(np.prod(L))
+        if s.phase == "cd":
+            site = lat / b0 * L
+            d = x - site
+            d -= L * np.round(d / L)
+            x0 = site + d.mean(axis=0)
+            k = 3.0 * est.KB * T / np.mean(msd[q])
+            sw_specs.append(inputs.SystemSpec(x=x0 + (d - d.mean(axis=0)), v=eng.velocities(q), box=L, phase="cd",
+                                              x0=x0, mode=inputs.MODE_FL, k_spring=k, T0=T, tau_damp=0.1,
+                                              stream=100 + q))
+            info.append(dict(phase="cd", n=s.n, V=V, k=k, h=np.mean(u[q])))
+        else:
+            sw_specs.append(inputs.SystemSpec(x=x, v=eng.velocities(q), box=L, phase="liq", mode=inputs.MODE_UF,
+                                              T0=T, tau_damp=0.1, stream=100 + q, **UF))
+            g = inputs.rng(998, q, 4)
+            gas_specs.append(inputs.SystemSpec(x=g.random((s.n, 3)) * L, v=inputs.maxwell(s.n, T, inputs.rng(998, q, 5)),
+                                               box=L, phase="gas", mode=inputs.MODE_UF, T0=T, tau_damp=0.1,
+                                               stream=200 + q, **UF))
+            info.append(dict(phase="liq", n=s.n, V=V, h=np.mean(u[q])))
+    eng.close()
+
+    eng = swfe.Engine(sw_specs, sw_params, dt=0.001, seed=22, precision="mixed")
+    eng.set_skin(1.0)
+    wf, wb = _switch(eng, sw_specs, N_HOLD, N_SW)
+    assert not any(s["err"] for s in eng.state())
+    eng.close()
+    P0 = dict(sw_params)
+    P0["epsilon"] = 0.0                      # SW off: lambda = 1 is the ideal gas
+    eng = swfe.Engine(gas_specs, P0, dt=0.001, seed=23, precision="mixed")
+    eng.set_skin(1.0)
+    gf, gb = _switch(eng, gas_specs, N_HOLD, N_SW)
+    assert not any(s["err"] for s in eng.state())
+    eng.close()
+
+    out = {"cd": [], "liq": []}
+    i_sw = 0
+    i_gas = 0
+    for d in info:
+        if d["phase"] == "cd":
+            F = est.solid_free_energy(d["n"], d["k"], T, inputs.SI_MASS_AMU, d["V"], [wf[i_sw]], [wb[i_sw]])
+            diss = est.dissipated_heat([wf[i_sw]], [wb[i_sw]]) / d["n"]
+        else:
+            F = est.liquid_free_energy(d["n"], d["V"], T, inputs.SI_MASS_AMU, [gf[i_gas]], [gb[i_gas]],
+                                       [wf[i_sw]], [wb[i_sw]])
+            diss = max(est.dissipated_heat([wf[i_sw]], [wb[i_sw]]), est.dissipated_heat([gf[i_gas]], [gb[i_gas]])) / d["n"]
+            i_gas += 1
+        i_sw += 1
+        g = F / d["n"]
+        out[d["phase"]].append((g, d["h"], d["V"] / d["n"], diss))
+        print(f"{d['phase']}: v {d['V'] / d['n']:.4f} A^3, u {d['h']:.5f} eV, g {g:.6f} eV, "
+              f"dissipated {1e3 * diss:.3f} meV/atom" + (f", k {d['k']:.3f} eV/A^2" if "k" in d else ""), flush=True)
+    return {p: np.array(v) for p, v in out.items()}
+
+
+def test_melting_temperature_at_zero_pressure(phases):
+    cd, liq = phases["cd"], phases["liq"]
+    Tm = est.transition_temperature(T, cd[:, 0].mean(), cd[:, 1].mean(), liq[:, 0].mean(), liq[:, 1].mean())
+    dg = liq[:, 0].mean() - cd[:, 0].mean()
+    sem = np.hypot(cd[:, 0].std(ddof=1), liq[:, 0].std(ddof=1)) / np.sqrt(REAL)
+    dT = T * sem / (liq[:, 1].mean() - cd[:, 1].mean())
+    print(f"g(liquid) - g(cd) at {T} K: {1e3 * dg:.3f} meV/atom, latent heat "
+          f"{liq[:, 1].mean() - cd[:, 1].mean():.4f} eV/atom; T_m(0 GPa) = {Tm:.1f} +- {dT:.1f} K "
+          f"(paper 1689.2(3))", flush=True)
+    assert abs(Tm - 1689.2) < 40.0
