@@ -1,23 +1,27 @@
-"""The melting temperature of Stillinger-Weber silicon at zero pressure from
-absolute free energies (section 2.1, section 4.1), the paper's T_m(0 GPa) =
-1689.2(3) K.
+"""Melting temperatures of Stillinger-Weber silicon from absolute free
+energies (section 2.1, section 4.1): the paper's T_m(0 GPa) = 1689.2(3) K
+(diamond) and T_m(15 GPa) = 1365.3(3) K (beta-tin).
 
-Both phases at (1689.2 K, 0 GPa) after NPT equilibration:
-* diamond (4096 atoms): Frenkel-Ladd switching to its Einstein crystal at
-  its mean box, springs matched to the measured fluctuations;
+Both phases at the paper's (T_m, P) after NPT equilibration:
+* the crystal (4096-atom diamond with one piston, or 8000-atom beta-tin
+  with one piston per axis): Frenkel-Ladd switching to its Einstein crystal
+  at its mean box, springs matched to the measured fluctuations;
 * liquid (3000 atoms): the SW liquid switched to the Uhlenbeck-Ford fluid
   (p = 25, sigma = 2 A, cutoff 8 A) at its mean volume, and an ideal gas in
   the same box switched on to the same UF fluid, so that F_liquid = F_gas +
   (F_UF - F_gas) - (F_UF - F_liquid) with no tabulated UF free energy.
-The per-atom Gibbs energies (g = F / N at P = 0) and enthalpies (the mean
-potential energy per atom; the kinetic parts are equal) give the crossing
-temperature.  Four realisations of each phase, 100 ps per switching
-direction, mixed precision.
+The per-atom Gibbs energies (g = F / N + P v) and enthalpies (u + P v, u
+the mean potential energy per atom; the kinetic parts are equal) give the
+crossing temperature.  Four realisations of each phase, 100 ps per
+switching direction, mixed precision.
 
-Measured: T_m(0 GPa) = 1684.8 +- 1.9 K (paper 1689.2(3)); g(liquid) -
+Measured at 0 GPa: T_m = 1684.8 +- 1.9 K (paper 1689.2(3)); g(liquid) -
 g(cd) = -0.85 meV/atom at 1689.2 K, latent heat 0.323 eV/atom, liquid
 18.87 A^3/atom against 20.35 for the crystal; dissipated heat 0.05-0.4
-meV/atom (crystal) and about 3.5 meV/atom (liquid legs)."""
+meV/atom (crystal) and about 3.5 meV/atom (liquid legs).  At 15 GPa: T_m =
+1365.3 +- 1.1 K (paper 1365.3(3)); g(liquid) - g(beta-tin) = -0.001
+meV/atom at 1365.3 K, latent heat 0.140 eV/atom, liquid 17.05 A^3/atom
+against 16.60 for beta-tin."""
 import numpy as np
 import pytest
 
@@ -26,10 +30,17 @@ from paper_2103_10449_amd import inputs
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-T = 1689.2
+CASES = {"cd_0GPa": ("cd", 1689.2, 0.0), "bt_15GPa": ("bt", 1365.3, 15.0)}  # crystal, paper's T_m (K), P (GPa)
 N_LIQ, REAL = 3000, 4
 N_EQ, N_AVG, N_HOLD, N_SW = 30000, 20000, 10000, 100000
-UF = dict(uf_p=inputs.UF_P, uf_sigma=inputs.UF_SIGMA, uf_T=T, uf_rcut=inputs.UF_RCUT)
+
+
+def _crystal(kind):
+    if kind == "cd":
+        x, b = inputs.diamond((8, 8, 8), 5.431)
+        return x, b, inputs.BARO_ISO
+    x, b = inputs.beta_sn((10, 10, 20), 4.80, 2.65)
+    return x, b, inputs.BARO_ANISO
 
 
 def _switch(eng, specs, n_hold, n_sw):
@@ -48,21 +59,24 @@ def _switch(eng, specs, n_hold, n_sw):
     return wf, wb
 
 
-@pytest.fixture(scope="module")
-def phases(sw_params):
+@pytest.fixture(scope="module", params=list(CASES))
+def phases(request, sw_params):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2103_10449_amd import swfe
-    lat, b0 = inputs.diamond((8, 8, 8), 5.431)
+    kind, T, P = CASES[request.param]
+    UF = dict(uf_p=inputs.UF_P, uf_sigma=inputs.UF_SIGMA, uf_T=T, uf_rcut=inputs.UF_RCUT)
+    lat, b0, baro = _crystal(kind)
+    print(f"{request.param}: {kind} {len(lat)} atoms and liquid {N_LIQ} atoms at {T} K, {P} GPa", flush=True)
     npt = []
     for r in range(REAL):
         npt.append(inputs.SystemSpec(x=lat, v=inputs.maxwell(len(lat), T, inputs.rng(998, r, 1)), box=b0,
-                                     phase="cd", mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0,
-                                     pressure=0.0, stream=2 * r))
+                                     phase="crystal", mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0,
+                                     pressure=P, stream=2 * r, baro=baro))
         x, b = inputs.liquid_rsa(N_LIQ, inputs.rng(998, r, 2))
         npt.append(inputs.SystemSpec(x=x, v=inputs.maxwell(N_LIQ, T, inputs.rng(998, r, 3)), box=b, phase="liq",
-                                     mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=0.0,
+                                     mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=P,
                                      stream=2 * r + 1))
     eng = swfe.Engine(npt, sw_params, dt=0.001, seed=21, precision="mixed")
     eng.set_skin(1.0)
@@ -75,8 +89,8 @@ def phases(sw_params):
         st = eng.state()
         for q, s in enumerate(npt):
             boxes[q].append(st[q]["box"])
-            u[q].append(st[q]["U_int"] / s.n)
-            if s.phase == "cd":
+            u[q].append((st[q]["U_int"] + P * est.EV_A3_PER_GPA * st[q]["V"]) / s.n)   # enthalpy less K
+            if s.phase == "crystal":
                 L = st[q]["box"]
                 d = eng.positions(q) - lat / b0 * L
                 d -= L * np.round(d / L)
@@ -89,16 +103,16 @@ def phases(sw_params):
         L = np.mean(boxes[q], axis=0)
         x = eng.positions(q) * (L / st[q]["box"])
         V = float(np.prod(L))
-        if s.phase == "cd":
+        if s.phase == "crystal":
             site = lat / b0 * L
             d = x - site
             d -= L * np.round(d / L)
             x0 = site + d.mean(axis=0)
             k = 3.0 * est.KB * T / np.mean(msd[q])
-            sw_specs.append(inputs.SystemSpec(x=x0 + (d - d.mean(axis=0)), v=eng.velocities(q), box=L, phase="cd",
+            sw_specs.append(inputs.SystemSpec(x=x0 + (d - d.mean(axis=0)), v=eng.velocities(q), box=L, phase="crystal",
                                               x0=x0, mode=inputs.MODE_FL, k_spring=k, T0=T, tau_damp=0.1,
                                               stream=100 + q))
-            info.append(dict(phase="cd", n=s.n, V=V, k=k, h=np.mean(u[q])))
+            info.append(dict(phase="crystal", n=s.n, V=V, k=k, h=np.mean(u[q])))
         else:
             sw_specs.append(inputs.SystemSpec(x=x, v=eng.velocities(q), box=L, phase="liq", mode=inputs.MODE_UF,
                                               T0=T, tau_damp=0.1, stream=100 + q, **UF))
@@ -122,11 +136,11 @@ def phases(sw_params):
     assert not any(s["err"] for s in eng.state())
     eng.close()
 
-    out = {"cd": [], "liq": []}
+    out = {"crystal": [], "liq": []}
     i_sw = 0
     i_gas = 0
     for d in info:
-        if d["phase"] == "cd":
+        if d["phase"] == "crystal":
             F = est.solid_free_energy(d["n"], d["k"], T, inputs.SI_MASS_AMU, d["V"], [wf[i_sw]], [wb[i_sw]])
             diss = est.dissipated_heat([wf[i_sw]], [wb[i_sw]]) / d["n"]
         else:
@@ -135,20 +149,22 @@ def phases(sw_params):
             diss = max(est.dissipated_heat([wf[i_sw]], [wb[i_sw]]), est.dissipated_heat([gf[i_gas]], [gb[i_gas]])) / d["n"]
             i_gas += 1
         i_sw += 1
-        g = F / d["n"]
+        g = F / d["n"] + P * est.EV_A3_PER_GPA * d["V"] / d["n"]
         out[d["phase"]].append((g, d["h"], d["V"] / d["n"], diss))
-        print(f"{d['phase']}: v {d['V'] / d['n']:.4f} A^3, u {d['h']:.5f} eV, g {g:.6f} eV, "
+        print(f"{d['phase']}: v {d['V'] / d['n']:.4f} A^3, h {d['h']:.5f} eV, g {g:.6f} eV, "
               f"dissipated {1e3 * diss:.3f} meV/atom" + (f", k {d['k']:.3f} eV/A^2" if "k" in d else ""), flush=True)
-    return {p: np.array(v) for p, v in out.items()}
+    return request.param, {p: np.array(v) for p, v in out.items()}
 
 
-def test_melting_temperature_at_zero_pressure(phases):
-    cd, liq = phases["cd"], phases["liq"]
-    Tm = est.transition_temperature(T, cd[:, 0].mean(), cd[:, 1].mean(), liq[:, 0].mean(), liq[:, 1].mean())
-    dg = liq[:, 0].mean() - cd[:, 0].mean()
-    sem = np.hypot(cd[:, 0].std(ddof=1), liq[:, 0].std(ddof=1)) / np.sqrt(REAL)
-    dT = T * sem / (liq[:, 1].mean() - cd[:, 1].mean())
-    print(f"g(liquid) - g(cd) at {T} K: {1e3 * dg:.3f} meV/atom, latent heat "
-          f"{liq[:, 1].mean() - cd[:, 1].mean():.4f} eV/atom; T_m(0 GPa) = {Tm:.1f} +- {dT:.1f} K "
-          f"(paper 1689.2(3))", flush=True)
-    assert abs(Tm - 1689.2) < 40.0
+def test_melting_temperature(phases):
+    name, ph = phases
+    kind, T, P = CASES[name]
+    cr, liq = ph["crystal"], ph["liq"]
+    Tm = est.transition_temperature(T, cr[:, 0].mean(), cr[:, 1].mean(), liq[:, 0].mean(), liq[:, 1].mean())
+    dg = liq[:, 0].mean() - cr[:, 0].mean()
+    sem = np.hypot(cr[:, 0].std(ddof=1), liq[:, 0].std(ddof=1)) / np.sqrt(REAL)
+    dT = T * sem / (liq[:, 1].mean() - cr[:, 1].mean())
+    print(f"{name}: g(liquid) - g({kind}) at {T} K: {1e3 * dg:.3f} meV/atom, latent heat "
+          f"{liq[:, 1].mean() - cr[:, 1].mean():.4f} eV/atom; T_m({P} GPa) = {Tm:.1f} +- {dT:.1f} K "
+          f"(paper {T}(3))", flush=True)
+    assert abs(Tm - T) < 40.0
