@@ -7,10 +7,11 @@
  * runs and dynamic Clausius-Clapeyron integration (dCCI):
  *   - cell-list neighbour build,
  *   - Stillinger-Weber energy, force, virial and parameter gradient,
- *   - velocity Verlet with a Langevin thermostat and an isotropic barostat,
+ *   - velocity Verlet with a Langevin thermostat and an isotropic or
+ *     per-axis barostat,
  *   - the lambda-switched Hamiltonian and its dH/dlambda work integral for
- *     Frenkel-Ladd, reversible-scaling, pressure-switching and coupled-phase
- *     dCCI runs.
+ *     Frenkel-Ladd (Einstein reference), Uhlenbeck-Ford (liquid reference),
+ *     reversible-scaling, pressure-switching and coupled-phase dCCI runs.
  * Passages of the paper are cited as section / equation labels of
  * "Non-equilibrium free-energy calculation of phase-boundaries using LAMMPS"
  * (Cajahuaringa and Antonelli).
@@ -44,7 +45,8 @@ typedef struct swfe_ctx swfe_ctx;
 #define SWFE_OK 0
 #define SWFE_E_INVALID_ARG -1   /* bad pointer, size, mode or parameter */
 #define SWFE_E_BOX_TOO_SMALL -2 /* a box length below twice the cutoff */
-#define SWFE_E_OVERFLOW -3      /* Verlet list (64 per atom) overflowed */
+#define SWFE_E_OVERFLOW -3      /* a neighbour list overflowed: the Verlet list (64 per atom,
+                                   more with a UF reference) or the 48 pairs within the cutoff */
 #define SWFE_E_NONFINITE -4     /* NaN/Inf in an energy, force or position */
 #define SWFE_E_DCCI_SINGULAR -5 /* dCCI denominator or lambda out of range */
 #define SWFE_E_HIP -6           /* a HIP runtime call failed */
@@ -145,7 +147,7 @@ typedef struct {
     double Ps;         /* barostat target (scaled pressure P_S), GPa */
     double W;          /* accumulated work, eV */
     double U_int;      /* unscaled interaction energy at the current positions */
-    double U_ref;      /* Einstein energy (FL) */
+    double U_ref;      /* reference energy: Einstein (FL), Uhlenbeck-Ford (UF) */
     double K;          /* kinetic energy, eV */
     double V;          /* volume, A^3 */
     double virial[9];  /* dU_int/dstrain (eV), row-major */
@@ -185,8 +187,9 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys,
                      const swfe_sw_params *p, const swfe_buffers *b, uint64_t seed, double dt,
                      int32_t precision, void *stream);
 
-/* Cell binning of the current positions (step a1): cell index per atom,
- * deterministic counting sort by cell (ties in atom order). */
+/* Neighbour build at the current positions (step a1): cell index per atom,
+ * deterministic counting sort by cell (ties in atom order), and the Verlet
+ * lists of every system. */
 int swfe_build_neighbors(swfe_ctx *ctx, void *stream);
 
 /* Interaction at the current positions: binning, pair terms and three-body
