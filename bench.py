@@ -147,7 +147,8 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
 def per_config_rates(P, seed, steps=200):
     """Atom-steps/s of the smaller single-workload configurations (mixed and
     FP64), each alone on the GPU: the 64-atom Frenkel-Ladd crystal, the
-    8000-atom diamond and liquid reversible-scaling runs, the dCCI pair of
+    8000-atom diamond and liquid reversible-scaling runs (and their force
+    evaluations per second), the dCCI pair of
     4096-atom diamond and 8000-atom beta-tin; and force evaluations per
     second (with the forced list build) of the 32768-atom crystal.  Small
     systems are bound by the launch sequence, not by the atoms."""
@@ -171,8 +172,17 @@ def per_config_rates(P, seed, steps=200):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             eng.state()
-            eng.close()
             row[prec] = wl.n_atoms * steps / dt
+            if name.startswith("c2"):
+                # force-only throughput (with the forced list build) of the same system
+                eng.compute_forces()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(20):
+                    eng.compute_forces()
+                torch.cuda.synchronize()
+                row[prec + "_forces_atoms_per_s"] = wl.n_atoms * 20 / (time.perf_counter() - t0)
+            eng.close()
         out[name] = row
         print(f"# per-config {name}: {row}", file=sys.stderr, flush=True)
     wl = inputs.config5()
