@@ -38,16 +38,20 @@ PEAK_HBM = 8.0e12                             # B/s
 SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
 
 # HBM bytes per launch of the force passes on this workload (64 replicas,
-# mixed precision, skin 1.4 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# (KiB per dispatch, averaged over the dispatches of a short run), each
-# scaled by what the counter reads for a plain 512 MiB device copy: FETCH_SIZE
-# reads half the copied bytes (factor 2.000), WRITE_SIZE all of them (1.000).
-# The figures hold only for the kernel sources they were taken on (digest).
+# skin 1.4 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+# averaged over the dispatches of a short run of both precisions), each
+# scaled by what the counter reads for a plain 512 MiB device copy:
+# FETCH_SIZE reads half the copied bytes (factor 2.000), WRITE_SIZE all of
+# them (1.000).  The figures hold only for the kernel sources they were taken
+# on (digest).
 MEASURED_TRAFFIC = {
     "sources_sha256": "272f1c6413c233a36698189de59c593529c3bbe40afa073d6dfb91f94d5347ac",
-    "skin": 1.4, "replicas": 64, "precision": "mixed",
+    "skin": 1.4, "replicas": 64,
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "kib": {"pass1": (24302.4, 43740.1), "pass2": (34190.9, 23387.6)},  # (FETCH_SIZE, WRITE_SIZE)
+    "kib": {  # (FETCH_SIZE, WRITE_SIZE)
+        ("mixed", "pass1"): (24299.8, 43714.7), ("mixed", "pass2"): (34173.8, 23380.7),
+        ("fp64", "pass1"): (22900.5, 47048.3), ("fp64", "pass2"): (32991.6, 23149.7),
+    },
 }
 
 
@@ -64,10 +68,11 @@ def measured_traffic(name, skin, replicas, precision):
     """HBM bytes per launch of kernel `name`, or None when the counters were
     not taken on this configuration and these kernel sources."""
     m = MEASURED_TRAFFIC
-    if (name not in m["kib"] or skin != m["skin"] or replicas != m["replicas"] or precision != m["precision"]
+    key = (precision, name)
+    if (key not in m["kib"] or skin != m["skin"] or replicas != m["replicas"]
             or kernel_sources_digest() != m["sources_sha256"]):
         return None
-    fetch, write = m["kib"][name]
+    fetch, write = m["kib"][key]
     return 1024.0 * (fetch * m["fetch_factor"] + write * m["write_factor"])
 
 
@@ -368,8 +373,12 @@ def main():
             p64 = fp64["prof"]
             avg64 = p64[name] / n_prof / 1e3
             fl64 = kernel_flops(name, fp64["n_atoms"], fp64["pairs"])
+            tr64 = measured_traffic(name, fp64["skin"], args.replicas, "fp64")
             out["roofline_fp64"] = {"kernel": name, "achieved": fl64 / avg64 / 1e12, "peak": PEAK["fp64"] / 1e12,
-                                    "frac": fl64 / avg64 / PEAK["fp64"],
+                                    "frac": fl64 / avg64 / PEAK["fp64"], "traffic": tr64,
+                                    "avg_launch_us": 1e6 * avg64,
+                                    "hbm_GBps": tr64 / avg64 / 1e9 if tr64 else None,
+                                    "hbm_frac": tr64 / avg64 / PEAK_HBM if tr64 else None,
                                     "per_kernel_us": {k: 1e3 * v / n_prof for k, v in p64.items()}}
     if cpu is not None:
         out["cpu_baseline"] = cpu
