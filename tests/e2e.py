@@ -1,0 +1,295 @@
+"""End-to-end runs of the method on the GPU shared by several test modules:
+absolute free energies of the crystals and the liquid, and dCCI coexistence
+lines.  Each run is computed once per test session (see `cached`)."""
+import numpy as np
+
+from paper_2103_10449_amd import estimators as est
+from paper_2103_10449_amd import inputs
+
+_CACHE = {}
+
+
+def cached(key, fn, *args):
+    """fn(*args), computed once per process under `key`."""
+    if key not in _CACHE:
+        _CACHE[key] = fn(*args)
+    return _CACHE[key]
+
+
+def _solid(kind):
+    if kind == "cd":
+        x, b = inputs.diamond((8, 8, 8), 5.431)
+        return x, b, inputs.BARO_ISO
+    x, b = inputs.beta_sn((10, 10, 20), 4.80, 2.65)
+    return x, b, inputs.BARO_ANISO
+
+
+# ---- cd / beta-tin at 400 K: Frenkel-Ladd of both crystals at 13 GPa
+CO_T, CO_P = 400.0, 13.0
+CO_N_EQ, CO_N_AVG, CO_N_HOLD, CO_N_SW, CO_REAL = 20000, 20000, 10000, 100000, 4
+
+
+def coexistence_phases(sw_params):
+    """Absolute per-atom (g, v, dissipated heat, k) of diamond and beta-tin
+    at (400 K, 13 GPa), four realisations each (Frenkel-Ladd)."""
+    from paper_2103_10449_amd import swfe
+    T, P = CO_T, CO_P
+    kinds = [kind for _ in range(CO_REAL) for kind in ("cd", "bt")]
+    npt = []
+    for q, kind in enumerate(kinds):
+        x, b, baro = _solid(kind)
+        npt.append(inputs.SystemSpec(x=x, v=inputs.maxwell(len(x), T, inputs.rng(996, q, 1)), box=b, phase=kind,
+                                     mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=P,
+                                     stream=q, baro=baro))
+    eng = swfe.Engine(npt, sw_params, dt=0.001, seed=11, precision="mixed")
+    eng.set_skin(1.0)
+    eng.step(CO_N_EQ)
+    # mean box over the averaging window, and the mean-square displacement
+    # from the lattice sites (scaled to the box, centre of mass aligned)
+    boxes = [[] for _ in kinds]
+    msd = [[] for _ in kinds]
+    for _ in range(CO_N_AVG // 1000):
+        eng.step(1000)
+        st = eng.state()
+        for q, kind in enumerate(kinds):
+            L = st[q]["box"]
+            boxes[q].append(L)
+            site = _solid(kind)[0] / _solid(kind)[1] * L
+            d = eng.positions(q) - site
+            d -= L * np.round(d / L)
+            d -= d.mean(axis=0)
+            msd[q].append(np.mean(np.sum(d * d, axis=1)))
+    st = eng.state()
+    fl = []
+    info = []
+    for q, kind in enumerate(kinds):
+        lat, b0, _ = _solid(kind)
+        L = np.mean(boxes[q], axis=0)
+        x = eng.positions(q) * (L / st[q]["box"])
+        site = lat / b0 * L
+        d = x - site
+        d -= L * np.round(d / L)
+        x0 = site + d.mean(axis=0)
+        k = 3.0 * est.KB * T / np.mean(msd[q])
+        fl.append(inputs.SystemSpec(x=x0 + (d - d.mean(axis=0)), v=eng.velocities(q), box=L, phase=kind, x0=x0,
+                                    mode=inputs.MODE_FL, k_spring=k, T0=T, tau_damp=0.1, stream=100 + q,
+                                    sched_start=1.0, sched_end=1.0, sched_steps=0))
+        info.append(dict(kind=kind, n=len(lat), V=float(np.prod(L)), k=k))
+    assert not any(s["err"] for s in st)
+    eng.close()
+
+    eng = swfe.Engine(fl, sw_params, dt=0.001, seed=12, precision="mixed")
+    eng.set_skin(1.0)
+
+    def run(a, b, n):
+        for s in fl:
+            s.sched_start, s.sched_end, s.sched_steps = a, b, n
+        eng.set_schedule(fl)
+        eng.step(n if n else CO_N_HOLD)
+        return eng.work_integral()["W"]
+
+    run(1.0, 1.0, 0)
+    wf = run(1.0, 0.0, CO_N_SW)
+    run(0.0, 0.0, 0)
+    wb = run(0.0, 1.0, CO_N_SW)
+    assert not any(s["err"] for s in eng.state())
+    eng.close()
+    out = {"cd": [], "bt": []}
+    for q, d in enumerate(info):
+        F = est.solid_free_energy(d["n"], d["k"], T, inputs.SI_MASS_AMU, d["V"], [wf[q]], [wb[q]])
+        v = d["V"] / d["n"]
+        g = F / d["n"] + P * est.EV_A3_PER_GPA * v
+        diss = est.dissipated_heat([wf[q]], [wb[q]]) / d["n"]
+        out[d["kind"]].append((g, v, diss, d["k"]))
+        print(f"{d['kind']}: k {d['k']:.3f} eV/A^2, v {v:.4f} A^3, g {g:.6f} eV, "
+              f"dissipated {1e3 * diss:.3f} meV/atom", flush=True)
+    return {kind: np.array(v) for kind, v in out.items()}
+
+
+def coexistence_pressure(ph):
+    cd, bt = ph["cd"], ph["bt"]
+    return est.coexistence_pressure(CO_P, cd[:, 0].mean(), cd[:, 1].mean(), bt[:, 0].mean(), bt[:, 1].mean())
+
+
+# ---- melting points: crystal by Frenkel-Ladd, liquid through the UF fluid
+MELT_CASES = {"cd_0GPa": ("cd", 1689.2, 0.0), "bt_15GPa": ("bt", 1365.3, 15.0)}  # crystal, paper's T_m (K), P (GPa)
+ME_N_LIQ, ME_REAL = 3000, 4
+ME_N_EQ, ME_N_AVG, ME_N_HOLD, ME_N_SW = 30000, 20000, 10000, 100000
+
+
+def _switch(eng, specs, n_hold, n_sw):
+    """Hold at lambda = 1, switch 1 -> 0, hold at 0, switch 0 -> 1; the work of
+    each switching leg per system."""
+    def leg(a, b, n):
+        for s in specs:
+            s.sched_start, s.sched_end, s.sched_steps = a, b, n
+        eng.set_schedule(specs)
+        eng.step(n if n else n_hold)
+        return eng.work_integral()["W"].copy()
+    leg(1.0, 1.0, 0)
+    wf = leg(1.0, 0.0, n_sw)
+    leg(0.0, 0.0, 0)
+    wb = leg(0.0, 1.0, n_sw)
+    return wf, wb
+
+
+def melting_phases(sw_params, case):
+    """Absolute per-atom (g, h, v, dissipated heat) of a crystal and the
+    liquid at the paper's melting point `case` (MELT_CASES)."""
+    from paper_2103_10449_amd import swfe
+    kind, T, P = MELT_CASES[case]
+    UF = dict(uf_p=inputs.UF_P, uf_sigma=inputs.UF_SIGMA, uf_T=T, uf_rcut=inputs.UF_RCUT)
+    lat, b0, baro = _solid(kind)
+    print(f"{case}: {kind} {len(lat)} atoms and liquid {ME_N_LIQ} atoms at {T} K, {P} GPa", flush=True)
+    npt = []
+    for r in range(ME_REAL):
+        npt.append(inputs.SystemSpec(x=lat, v=inputs.maxwell(len(lat), T, inputs.rng(998, r, 1)), box=b0,
+                                     phase="crystal", mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0,
+                                     pressure=P, stream=2 * r, baro=baro))
+        x, b = inputs.liquid_rsa(ME_N_LIQ, inputs.rng(998, r, 2))
+        npt.append(inputs.SystemSpec(x=x, v=inputs.maxwell(ME_N_LIQ, T, inputs.rng(998, r, 3)), box=b, phase="liq",
+                                     mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=P,
+                                     stream=2 * r + 1))
+    eng = swfe.Engine(npt, sw_params, dt=0.001, seed=21, precision="mixed")
+    eng.set_skin(1.0)
+    eng.step(ME_N_EQ)
+    boxes = [[] for _ in npt]
+    u = [[] for _ in npt]
+    msd = [[] for _ in npt]
+    for _ in range(ME_N_AVG // 1000):
+        eng.step(1000)
+        st = eng.state()
+        for q, s in enumerate(npt):
+            boxes[q].append(st[q]["box"])
+            u[q].append((st[q]["U_int"] + P * est.EV_A3_PER_GPA * st[q]["V"]) / s.n)   # enthalpy less K
+            if s.phase == "crystal":
+                L = st[q]["box"]
+                d = eng.positions(q) - lat / b0 * L
+                d -= L * np.round(d / L)
+                d -= d.mean(axis=0)
+                msd[q].append(np.mean(np.sum(d * d, axis=1)))
+    st = eng.state()
+    assert not any(s["err"] for s in st)
+    sw_specs, gas_specs, info = [], [], []
+    for q, s in enumerate(npt):
+        L = np.mean(boxes[q], axis=0)
+        x = eng.positions(q) * (L / st[q]["box"])
+        V = float(np.prod(L))
+        if s.phase == "crystal":
+            site = lat / b0 * L
+            d = x - site
+            d -= L * np.round(d / L)
+            x0 = site + d.mean(axis=0)
+            k = 3.0 * est.KB * T / np.mean(msd[q])
+            sw_specs.append(inputs.SystemSpec(x=x0 + (d - d.mean(axis=0)), v=eng.velocities(q), box=L, phase="crystal",
+                                              x0=x0, mode=inputs.MODE_FL, k_spring=k, T0=T, tau_damp=0.1,
+                                              stream=100 + q))
+            info.append(dict(phase="crystal", n=s.n, V=V, k=k, h=np.mean(u[q])))
+        else:
+            sw_specs.append(inputs.SystemSpec(x=x, v=eng.velocities(q), box=L, phase="liq", mode=inputs.MODE_UF,
+                                              T0=T, tau_damp=0.1, stream=100 + q, **UF))
+            g = inputs.rng(998, q, 4)
+            gas_specs.append(inputs.SystemSpec(x=g.random((s.n, 3)) * L, v=inputs.maxwell(s.n, T, inputs.rng(998, q, 5)),
+                                               box=L, phase="gas", mode=inputs.MODE_UF, T0=T, tau_damp=0.1,
+                                               stream=200 + q, **UF))
+            info.append(dict(phase="liq", n=s.n, V=V, h=np.mean(u[q])))
+    eng.close()
+
+    eng = swfe.Engine(sw_specs, sw_params, dt=0.001, seed=22, precision="mixed")
+    eng.set_skin(1.0)
+    wf, wb = _switch(eng, sw_specs, ME_N_HOLD, ME_N_SW)
+    assert not any(s["err"] for s in eng.state())
+    eng.close()
+    P0 = dict(sw_params)
+    P0["epsilon"] = 0.0                      # SW off: lambda = 1 is the ideal gas
+    eng = swfe.Engine(gas_specs, P0, dt=0.001, seed=23, precision="mixed")
+    eng.set_skin(1.0)
+    gf, gb = _switch(eng, gas_specs, ME_N_HOLD, ME_N_SW)
+    assert not any(s["err"] for s in eng.state())
+    eng.close()
+
+    out = {"crystal": [], "liq": []}
+    i_sw = 0
+    i_gas = 0
+    for d in info:
+        if d["phase"] == "crystal":
+            F = est.solid_free_energy(d["n"], d["k"], T, inputs.SI_MASS_AMU, d["V"], [wf[i_sw]], [wb[i_sw]])
+            diss = est.dissipated_heat([wf[i_sw]], [wb[i_sw]]) / d["n"]
+        else:
+            F = est.liquid_free_energy(d["n"], d["V"], T, inputs.SI_MASS_AMU, [gf[i_gas]], [gb[i_gas]],
+                                       [wf[i_sw]], [wb[i_sw]])
+            diss = max(est.dissipated_heat([wf[i_sw]], [wb[i_sw]]), est.dissipated_heat([gf[i_gas]], [gb[i_gas]])) / d["n"]
+            i_gas += 1
+        i_sw += 1
+        g = F / d["n"] + P * est.EV_A3_PER_GPA * d["V"] / d["n"]
+        out[d["phase"]].append((g, d["h"], d["V"] / d["n"], diss))
+        print(f"{d['phase']}: v {d['V'] / d['n']:.4f} A^3, h {d['h']:.5f} eV, g {g:.6f} eV, "
+              f"dissipated {1e3 * diss:.3f} meV/atom" + (f", k {d['k']:.3f} eV/A^2" if "k" in d else ""), flush=True)
+    return {p: np.array(v) for p, v in out.items()}
+
+
+def melting_temperature(case, ph):
+    kind, T, P = MELT_CASES[case]
+    cr, liq = ph["crystal"], ph["liq"]
+    return est.transition_temperature(T, cr[:, 0].mean(), cr[:, 1].mean(), liq[:, 0].mean(), liq[:, 1].mean())
+
+
+# ---- dCCI lines
+DC_N_EQ, DC_N_SW, DC_REAL = 30000, 100000, 2
+
+
+def _phase(kind, T, Pg, seed):
+    if kind == "cd":
+        x, b = inputs.diamond((8, 8, 8), 5.431)
+        baro = inputs.BARO_ISO
+    elif kind == "bt":
+        x, b = inputs.beta_sn((10, 10, 20), 4.80, 2.65)
+        baro = inputs.BARO_ANISO
+    else:
+        x, b = inputs.liquid_rsa(8000, inputs.rng(995, seed, 0))
+        baro = inputs.BARO_ISO
+    return inputs.SystemSpec(x=x, v=inputs.maxwell(len(x), T, inputs.rng(995, seed, 1)), box=b, phase=kind,
+                             mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=Pg, stream=seed,
+                             baro=baro)
+
+
+def dcci_curves(sw_params, lines, seed0=0):
+    """(T, P) along dCCI lines (phase I, phase II, T0, P0, mode, schedule start,
+    end) from their starting points, DC_REAL realisations each, all in one
+    batch; {pair index: (line index, array of (T, P))}."""
+    from paper_2103_10449_amd import swfe
+    jobs = [(r, i) for r in range(DC_REAL) for i in range(len(lines))]
+    eq = []
+    for r, i in jobs:
+        a, b, T, Pg = lines[i][:4]
+        eq += [_phase(a, T, Pg, seed0 + 100 * r + 2 * i), _phase(b, T, Pg, seed0 + 100 * r + 2 * i + 1)]
+    eng = swfe.Engine(eq, sw_params, dt=0.001, seed=7, precision="mixed")
+    eng.set_skin(1.0)
+    eng.step(DC_N_EQ)
+    st = eng.state()
+    specs = []
+    for q, (r, i) in enumerate(jobs):
+        a, b, T, Pg, mode, s0, s1 = lines[i]
+        for h in range(2):
+            k = 2 * q + h
+            specs.append(inputs.SystemSpec(
+                x=eng.positions(k), v=eng.velocities(k), box=st[k]["box"].copy(), phase=eq[k].phase, mode=mode,
+                partner=2 * q + 1 - h, T0=T, tau_damp=0.1, p_damp=1.0, pressure=Pg, stream=1000 + k,
+                baro=eq[k].baro, sched_start=s0, sched_end=s1, sched_steps=DC_N_SW))
+    eng.close()
+    eng = swfe.Engine(specs, sw_params, dt=0.001, seed=8, precision="mixed")
+    eng.set_skin(1.0)
+    # (T, P) of every pair along the schedule
+    out = {q: [] for q in range(len(jobs))}
+    for _ in range(DC_N_SW // 1000):
+        eng.step(1000)
+        st = eng.state()
+        for q, (r, i) in enumerate(jobs):
+            T0 = lines[i][2]
+            s = st[2 * q]
+            out[q].append((T0 / s["lam"], s["Ps"] / s["lam"]))
+    errs = [s["err"] for s in eng.state()]
+    eng.close()
+    assert not any(errs)
+    return {q: (jobs[q][1], np.array(v)) for q, v in out.items()}
+

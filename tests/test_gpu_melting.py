@@ -25,146 +25,24 @@ against 16.60 for beta-tin."""
 import numpy as np
 import pytest
 
-from paper_2103_10449_amd import estimators as est
-from paper_2103_10449_amd import inputs
+from tests import e2e
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-CASES = {"cd_0GPa": ("cd", 1689.2, 0.0), "bt_15GPa": ("bt", 1365.3, 15.0)}  # crystal, paper's T_m (K), P (GPa)
-N_LIQ, REAL = 3000, 4
-N_EQ, N_AVG, N_HOLD, N_SW = 30000, 20000, 10000, 100000
 
-
-def _crystal(kind):
-    if kind == "cd":
-        x, b = inputs.diamond((8, 8, 8), 5.431)
-        return x, b, inputs.BARO_ISO
-    x, b = inputs.beta_sn((10, 10, 20), 4.80, 2.65)
-    return x, b, inputs.BARO_ANISO
-
-
-def _switch(eng, specs, n_hold, n_sw):
-    """Hold at lambda = 1, switch 1 -> 0, hold at 0, switch 0 -> 1; the work of
-    each switching leg per system."""
-    def leg(a, b, n):
-        for s in specs:
-            s.sched_start, s.sched_end, s.sched_steps = a, b, n
-        eng.set_schedule(specs)
-        eng.step(n if n else n_hold)
-        return eng.work_integral()["W"].copy()
-    leg(1.0, 1.0, 0)
-    wf = leg(1.0, 0.0, n_sw)
-    leg(0.0, 0.0, 0)
-    wb = leg(0.0, 1.0, n_sw)
-    return wf, wb
-
-
-@pytest.fixture(scope="module", params=list(CASES))
-def phases(request, sw_params):
+@pytest.mark.parametrize("case", list(e2e.MELT_CASES))
+def test_melting_temperature(sw_params, case):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    from paper_2103_10449_amd import swfe
-    kind, T, P = CASES[request.param]
-    UF = dict(uf_p=inputs.UF_P, uf_sigma=inputs.UF_SIGMA, uf_T=T, uf_rcut=inputs.UF_RCUT)
-    lat, b0, baro = _crystal(kind)
-    print(f"{request.param}: {kind} {len(lat)} atoms and liquid {N_LIQ} atoms at {T} K, {P} GPa", flush=True)
-    npt = []
-    for r in range(REAL):
-        npt.append(inputs.SystemSpec(x=lat, v=inputs.maxwell(len(lat), T, inputs.rng(998, r, 1)), box=b0,
-                                     phase="crystal", mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0,
-                                     pressure=P, stream=2 * r, baro=baro))
-        x, b = inputs.liquid_rsa(N_LIQ, inputs.rng(998, r, 2))
-        npt.append(inputs.SystemSpec(x=x, v=inputs.maxwell(N_LIQ, T, inputs.rng(998, r, 3)), box=b, phase="liq",
-                                     mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=P,
-                                     stream=2 * r + 1))
-    eng = swfe.Engine(npt, sw_params, dt=0.001, seed=21, precision="mixed")
-    eng.set_skin(1.0)
-    eng.step(N_EQ)
-    boxes = [[] for _ in npt]
-    u = [[] for _ in npt]
-    msd = [[] for _ in npt]
-    for _ in range(N_AVG // 1000):
-        eng.step(1000)
-        st = eng.state()
-        for q, s in enumerate(npt):
-            boxes[q].append(st[q]["box"])
-            u[q].append((st[q]["U_int"] + P * est.EV_A3_PER_GPA * st[q]["V"]) / s.n)   # enthalpy less K
-            if s.phase == "crystal":
-                L = st[q]["box"]
-                d = eng.positions(q) - lat / b0 * L
-                d -= L * np.round(d / L)
-                d -= d.mean(axis=0)
-                msd[q].append(np.mean(np.sum(d * d, axis=1)))
-    st = eng.state()
-    assert not any(s["err"] for s in st)
-    sw_specs, gas_specs, info = [], [], []
-    for q, s in enumerate(npt):
-        L = np.mean(boxes[q], axis=0)
-        x = eng.positions(q) * (L / st[q]["box"])
-        V = float(np.prod(L))
-        if s.phase == "crystal":
-            site = lat / b0 * L
-            d = x - site
-            d -= L * np.round(d / L)
-            x0 = site + d.mean(axis=0)
-            k = 3.0 * est.KB * T / np.mean(msd[q])
-            sw_specs.append(inputs.SystemSpec(x=x0 + (d - d.mean(axis=0)), v=eng.velocities(q), box=L, phase="crystal",
-                                              x0=x0, mode=inputs.MODE_FL, k_spring=k, T0=T, tau_damp=0.1,
-                                              stream=100 + q))
-            info.append(dict(phase="crystal", n=s.n, V=V, k=k, h=np.mean(u[q])))
-        else:
-            sw_specs.append(inputs.SystemSpec(x=x, v=eng.velocities(q), box=L, phase="liq", mode=inputs.MODE_UF,
-                                              T0=T, tau_damp=0.1, stream=100 + q, **UF))
-            g = inputs.rng(998, q, 4)
-            gas_specs.append(inputs.SystemSpec(x=g.random((s.n, 3)) * L, v=inputs.maxwell(s.n, T, inputs.rng(998, q, 5)),
-                                               box=L, phase="gas", mode=inputs.MODE_UF, T0=T, tau_damp=0.1,
-                                               stream=200 + q, **UF))
-            info.append(dict(phase="liq", n=s.n, V=V, h=np.mean(u[q])))
-    eng.close()
-
-    eng = swfe.Engine(sw_specs, sw_params, dt=0.001, seed=22, precision="mixed")
-    eng.set_skin(1.0)
-    wf, wb = _switch(eng, sw_specs, N_HOLD, N_SW)
-    assert not any(s["err"] for s in eng.state())
-    eng.close()
-    P0 = dict(sw_params)
-    P0["epsilon"] = 0.0                      # SW off: lambda = 1 is the ideal gas
-    eng = swfe.Engine(gas_specs, P0, dt=0.001, seed=23, precision="mixed")
-    eng.set_skin(1.0)
-    gf, gb = _switch(eng, gas_specs, N_HOLD, N_SW)
-    assert not any(s["err"] for s in eng.state())
-    eng.close()
-
-    out = {"crystal": [], "liq": []}
-    i_sw = 0
-    i_gas = 0
-    for d in info:
-        if d["phase"] == "crystal":
-            F = est.solid_free_energy(d["n"], d["k"], T, inputs.SI_MASS_AMU, d["V"], [wf[i_sw]], [wb[i_sw]])
-            diss = est.dissipated_heat([wf[i_sw]], [wb[i_sw]]) / d["n"]
-        else:
-            F = est.liquid_free_energy(d["n"], d["V"], T, inputs.SI_MASS_AMU, [gf[i_gas]], [gb[i_gas]],
-                                       [wf[i_sw]], [wb[i_sw]])
-            diss = max(est.dissipated_heat([wf[i_sw]], [wb[i_sw]]), est.dissipated_heat([gf[i_gas]], [gb[i_gas]])) / d["n"]
-            i_gas += 1
-        i_sw += 1
-        g = F / d["n"] + P * est.EV_A3_PER_GPA * d["V"] / d["n"]
-        out[d["phase"]].append((g, d["h"], d["V"] / d["n"], diss))
-        print(f"{d['phase']}: v {d['V'] / d['n']:.4f} A^3, h {d['h']:.5f} eV, g {g:.6f} eV, "
-              f"dissipated {1e3 * diss:.3f} meV/atom" + (f", k {d['k']:.3f} eV/A^2" if "k" in d else ""), flush=True)
-    return request.param, {p: np.array(v) for p, v in out.items()}
-
-
-def test_melting_temperature(phases):
-    name, ph = phases
-    kind, T, P = CASES[name]
+    kind, T, P = e2e.MELT_CASES[case]
+    ph = e2e.cached(("melting", case), e2e.melting_phases, sw_params, case)
     cr, liq = ph["crystal"], ph["liq"]
-    Tm = est.transition_temperature(T, cr[:, 0].mean(), cr[:, 1].mean(), liq[:, 0].mean(), liq[:, 1].mean())
+    Tm = e2e.melting_temperature(case, ph)
     dg = liq[:, 0].mean() - cr[:, 0].mean()
-    sem = np.hypot(cr[:, 0].std(ddof=1), liq[:, 0].std(ddof=1)) / np.sqrt(REAL)
+    sem = np.hypot(cr[:, 0].std(ddof=1), liq[:, 0].std(ddof=1)) / np.sqrt(e2e.ME_REAL)
     dT = T * sem / (liq[:, 1].mean() - cr[:, 1].mean())
-    print(f"{name}: g(liquid) - g({kind}) at {T} K: {1e3 * dg:.3f} meV/atom, latent heat "
+    print(f"{case}: g(liquid) - g({kind}) at {T} K: {1e3 * dg:.3f} meV/atom, latent heat "
           f"{liq[:, 1].mean() - cr[:, 1].mean():.4f} eV/atom; T_m({P} GPa) = {Tm:.1f} +- {dT:.1f} K "
           f"(paper {T}(3))", flush=True)
     assert abs(Tm - T) < 40.0

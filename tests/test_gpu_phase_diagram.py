@@ -20,11 +20,21 @@ passes 1210 K at 10.12 +- 0.02 GPa (six realisations, insensitive to the
 equilibration length and barostat period), 0.2 GPa above the paper's
 crossing: this build's own absolute free energies put P_coex(400 K) at
 13.07 GPa, and an error d in the starting pressure reappears as d T / 400 K
-along the line (the line from 13.07 GPa passes 1210 K at 9.86 GPa)."""
+along the line (the line from 13.07 GPa passes 1210 K at 9.86 GPa).
+
+The same three lines are then run from this build's own starting points
+(its absolute free energies: P_coex(400 K), T_m(0 GPa), T_m(15 GPa), from
+the runs shared with the coexistence and melting tests) and must meet at
+the paper's triple point as well.  Measured: from 13.067 GPa, 1684.8 K and
+1365.3 K the melting lines cross at (1209.0 K, 9.89 GPa) and the
+cd/beta-tin line passes 1210 K at 9.78-9.88 GPa (two realisations per
+run); from the paper's points the melting lines cross at (1210.2 K, 9.935
+GPa) and the cd/beta-tin line passes 1210 K at 10.12-10.18 GPa."""
 import numpy as np
 import pytest
 
 from paper_2103_10449_amd import inputs
+from tests import e2e
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -33,22 +43,6 @@ LINES = [  # phase I, phase II, T0 (K), P0 (GPa), mode, schedule start, end
     ("cd", "liq", 1689.2, 0.0, inputs.MODE_DCCI_P, 0.0, 10.2),
     ("bt", "liq", 1365.3, 15.0, inputs.MODE_DCCI_P, 15.0, 9.4),
 ]
-N_EQ, N_SW, REAL = 30000, 100000, 2
-
-
-def _phase(kind, T, Pg, seed):
-    if kind == "cd":
-        x, b = inputs.diamond((8, 8, 8), 5.431)
-        baro = inputs.BARO_ISO
-    elif kind == "bt":
-        x, b = inputs.beta_sn((10, 10, 20), 4.80, 2.65)
-        baro = inputs.BARO_ANISO
-    else:
-        x, b = inputs.liquid_rsa(8000, inputs.rng(995, seed, 0))
-        baro = inputs.BARO_ISO
-    return inputs.SystemSpec(x=x, v=inputs.maxwell(len(x), T, inputs.rng(995, seed, 1)), box=b, phase=kind,
-                             mode=inputs.MODE_NVT, T0=T, tau_damp=0.1, p_damp=1.0, pressure=Pg, stream=seed,
-                             baro=baro)
 
 
 @pytest.fixture(scope="module")
@@ -56,49 +50,35 @@ def curves(sw_params):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    from paper_2103_10449_amd import swfe
-    jobs = [(r, i) for r in range(REAL) for i in range(len(LINES))]
-    eq = []
-    for r, i in jobs:
-        a, b, T, Pg = LINES[i][:4]
-        eq += [_phase(a, T, Pg, 100 * r + 2 * i), _phase(b, T, Pg, 100 * r + 2 * i + 1)]
-    eng = swfe.Engine(eq, sw_params, dt=0.001, seed=7, precision="mixed")
-    eng.set_skin(1.0)
-    eng.step(N_EQ)
-    st = eng.state()
-    specs = []
-    for q, (r, i) in enumerate(jobs):
-        a, b, T, Pg, mode, s0, s1 = LINES[i]
-        for h in range(2):
-            k = 2 * q + h
-            specs.append(inputs.SystemSpec(
-                x=eng.positions(k), v=eng.velocities(k), box=st[k]["box"].copy(), phase=eq[k].phase, mode=mode,
-                partner=2 * q + 1 - h, T0=T, tau_damp=0.1, p_damp=1.0, pressure=Pg, stream=1000 + k,
-                baro=eq[k].baro, sched_start=s0, sched_end=s1, sched_steps=N_SW))
-    eng.close()
-    eng = swfe.Engine(specs, sw_params, dt=0.001, seed=8, precision="mixed")
-    eng.set_skin(1.0)
-    # (T, P) of every pair along the schedule
-    out = {q: [] for q in range(len(jobs))}
-    for _ in range(N_SW // 1000):
-        eng.step(1000)
-        st = eng.state()
-        for q, (r, i) in enumerate(jobs):
-            T0 = LINES[i][2]
-            s = st[2 * q]
-            out[q].append((T0 / s["lam"], s["Ps"] / s["lam"]))
-    errs = [s["err"] for s in eng.state()]
-    eng.close()
-    assert not any(errs)
-    return {q: (jobs[q][1], np.array(v)) for q, v in out.items()}
+    return e2e.dcci_curves(sw_params, LINES)
 
 
 def _line(curves, i):
     return [tp for (li, tp) in curves.values() if li == i]
 
 
+def _cd_beta_tin_at_1210(curves):
+    return [np.interp(1210.0, tp[:, 0], tp[:, 1]) for tp in _line(curves, 0)]
+
+
+def _melting_crossing(curves):
+    """(T, P) where the mean cd/liquid and beta-tin/liquid lines cross."""
+    grid = np.linspace(9.45, 10.15, 141)
+
+    def mean_T(i):
+        vals = []
+        for tp in _line(curves, i):
+            o = np.argsort(tp[:, 1])
+            vals.append(np.interp(grid, tp[o, 1], tp[o, 0]))
+        return np.mean(vals, axis=0)
+
+    d = mean_T(1) - mean_T(2)
+    k = int(np.argmin(np.abs(d)))
+    return 0.5 * (mean_T(1)[k] + mean_T(2)[k]), grid[k]
+
+
 def test_cd_beta_tin_line_passes_the_triple_point(curves):
-    ps = [np.interp(1210.0, tp[:, 0], tp[:, 1]) for tp in _line(curves, 0)]
+    ps = _cd_beta_tin_at_1210(curves)
     print(f"cd/beta-tin: P(1210 K) = {np.round(ps, 3)} GPa, mean {np.mean(ps):.3f} (paper 9.90(3))", flush=True)
     assert abs(np.mean(ps) - 9.90) < 0.3
 
@@ -117,17 +97,29 @@ def test_melting_lines_reach_the_triple_point(curves, i):
 def test_melting_lines_cross_at_the_triple_point(curves):
     """The two melting lines (pressure control) cross within the tolerance
     of the paper's triple point."""
-    grid = np.linspace(9.45, 10.15, 141)
-
-    def mean_T(i):
-        vals = []
-        for tp in _line(curves, i):
-            o = np.argsort(tp[:, 1])
-            vals.append(np.interp(grid, tp[o, 1], tp[o, 0]))
-        return np.mean(vals, axis=0)
-
-    d = mean_T(1) - mean_T(2)
-    k = int(np.argmin(np.abs(d)))
-    Pt, Tt = grid[k], 0.5 * (mean_T(1)[k] + mean_T(2)[k])
+    Tt, Pt = _melting_crossing(curves)
     print(f"melting lines cross at ({Tt:.1f} K, {Pt:.3f} GPa); paper (1210(2) K, 9.90(3) GPa)", flush=True)
     assert abs(Tt - 1210.0) < 20.0 and abs(Pt - 9.90) < 0.3
+
+
+def test_lines_from_this_builds_own_starting_points_meet_at_the_triple_point(sw_params):
+    """All three starting points from this build's absolute free energies
+    (Frenkel-Ladd crystals, the liquid through the Uhlenbeck-Ford fluid),
+    then the three dCCI lines from them, two realisations each."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    Pc = float(e2e.coexistence_pressure(e2e.cached("coexistence", e2e.coexistence_phases, sw_params)))
+    Tm = {c: float(e2e.melting_temperature(c, e2e.cached(("melting", c), e2e.melting_phases, sw_params, c)))
+          for c in e2e.MELT_CASES}
+    own = [("cd", "bt", 400.0, Pc, inputs.MODE_DCCI_T, 400.0, 1250.0),
+           ("cd", "liq", Tm["cd_0GPa"], 0.0, inputs.MODE_DCCI_P, 0.0, 10.2),
+           ("bt", "liq", Tm["bt_15GPa"], 15.0, inputs.MODE_DCCI_P, 15.0, 9.4)]
+    curves = e2e.dcci_curves(sw_params, own, seed0=300)
+    ps = _cd_beta_tin_at_1210(curves)
+    Tt, Pt = _melting_crossing(curves)
+    print(f"from P_coex(400 K) = {Pc:.3f} GPa, T_m(0) = {Tm['cd_0GPa']:.1f} K, T_m(15 GPa) = "
+          f"{Tm['bt_15GPa']:.1f} K: melting lines cross at ({Tt:.1f} K, {Pt:.3f} GPa), cd/beta-tin line at "
+          f"{np.mean(ps):.3f} GPa at 1210 K; paper (1210(2) K, 9.90(3) GPa)", flush=True)
+    assert abs(Tt - 1210.0) < 20.0 and abs(Pt - 9.90) < 0.3
+    assert abs(np.mean(ps) - 9.90) < 0.3
