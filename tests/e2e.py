@@ -254,9 +254,11 @@ def _phase(kind, T, Pg, seed):
 
 
 def dcci_curves(sw_params, lines, seed0=0):
-    """(T, P) along dCCI lines (phase I, phase II, T0, P0, mode, schedule start,
-    end) from their starting points, DC_REAL realisations each, all in one
-    batch; {pair index: (line index, array of (T, P))}."""
+    """(T, P) every 1000 steps along dCCI lines (phase I, phase II, T0, P0,
+    mode, schedule start, end[, schedule steps; default DC_N_SW]) from their
+    starting points, DC_REAL realisations each, all in one batch, run for the
+    longest schedule (a line past its schedule holds its end point);
+    {pair index: (line index, array of (T, P))}."""
     from paper_2103_10449_amd import swfe
     jobs = [(r, i) for r in range(DC_REAL) for i in range(len(lines))]
     eq = []
@@ -268,20 +270,22 @@ def dcci_curves(sw_params, lines, seed0=0):
     eng.step(DC_N_EQ)
     st = eng.state()
     specs = []
+    n_run = max(line[7] if len(line) > 7 else DC_N_SW for line in lines)
     for q, (r, i) in enumerate(jobs):
-        a, b, T, Pg, mode, s0, s1 = lines[i]
+        a, b, T, Pg, mode, s0, s1 = lines[i][:7]
+        n_sw = lines[i][7] if len(lines[i]) > 7 else DC_N_SW
         for h in range(2):
             k = 2 * q + h
             specs.append(inputs.SystemSpec(
                 x=eng.positions(k), v=eng.velocities(k), box=st[k]["box"].copy(), phase=eq[k].phase, mode=mode,
                 partner=2 * q + 1 - h, T0=T, tau_damp=0.1, p_damp=1.0, pressure=Pg, stream=1000 + k,
-                baro=eq[k].baro, sched_start=s0, sched_end=s1, sched_steps=DC_N_SW))
+                baro=eq[k].baro, sched_start=s0, sched_end=s1, sched_steps=n_sw))
     eng.close()
     eng = swfe.Engine(specs, sw_params, dt=0.001, seed=8, precision="mixed")
     eng.set_skin(1.0)
     # (T, P) of every pair along the schedule
     out = {q: [] for q in range(len(jobs))}
-    for _ in range(DC_N_SW // 1000):
+    for _ in range(n_run // 1000):
         eng.step(1000)
         st = eng.state()
         for q, (r, i) in enumerate(jobs):
