@@ -1,10 +1,18 @@
 """End-to-end runs of the method on the GPU shared by several test modules:
 absolute free energies of the crystals and the liquid, and dCCI coexistence
 lines.  Each run is computed once per test session (see `cached`)."""
+import json
+import os
+
 import numpy as np
 
 from paper_2103_10449_amd import estimators as est
 from paper_2103_10449_amd import inputs
+
+# the paper's printed phase-boundary values (with their sections and figures)
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_phase_points.json")) as _f:
+    PAPER = json.load(_f)
+TRIPLE = (PAPER["triple_point"]["T"], PAPER["triple_point"]["P"])
 
 _CACHE = {}
 
@@ -112,7 +120,10 @@ def coexistence_pressure(ph):
 
 
 # ---- melting points: crystal by Frenkel-Ladd, liquid through the UF fluid
-MELT_CASES = {"cd_0GPa": ("cd", 1689.2, 0.0), "bt_15GPa": ("bt", 1365.3, 15.0)}  # crystal, paper's T_m (K), P (GPa)
+MELT_CASES = {  # crystal, the paper's T_m (K), P (GPa)
+    "cd_0GPa": ("cd", PAPER["melting_point_cd_0GPa"]["value"], 0.0),
+    "bt_15GPa": ("bt", PAPER["melting_point_beta_tin_15GPa"]["value"], 15.0),
+}
 ME_N_LIQ, ME_REAL = 3000, 4
 ME_N_EQ, ME_N_AVG, ME_N_HOLD, ME_N_SW = 30000, 20000, 10000, 100000
 

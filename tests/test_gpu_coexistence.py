@@ -1,7 +1,7 @@
 """Absolute free energies end to end: the cd / beta-tin coexistence pressure
 at 400 K from Frenkel-Ladd switching of both crystals (section 2.1, section
-4.1), the starting point the paper computes for its cd / beta-tin dCCI line
-(P_coex(400 K) = 13.17346(5) GPa).
+4.2), the starting point the paper computes for its cd / beta-tin dCCI line
+(P_coex(400 K) = 13.17346(5) GPa, tests/golden/paper_phase_points.json).
 
 Protocol: 4096-atom diamond (isotropic piston) and 8000-atom beta-tin (one
 piston per axis) equilibrated by NPT at 400 K and 13 GPa; each crystal is
@@ -49,7 +49,7 @@ def test_coexistence_pressure_at_400_K(phases):
     dP = sem / ((cd[:, 1].mean() - bt[:, 1].mean()) * est.EV_A3_PER_GPA)
     print(f"g(cd) - g(beta-tin) at {e2e.CO_P} GPa: {1e3 * (cd[:, 0].mean() - bt[:, 0].mean()):.3f} meV/atom; "
           f"P_coex(400 K) = {Pc:.3f} +- {dP:.3f} GPa (paper 13.17346(5))", flush=True)
-    assert abs(Pc - 13.17346) < 0.5
+    assert abs(Pc - e2e.PAPER["coexistence_pressure_cd_beta_tin_400K"]["value"]) < 0.5
 
 
 def test_dcci_line_from_the_computed_point_reaches_the_triple_point(sw_params, phases):
@@ -61,7 +61,8 @@ def test_dcci_line_from_the_computed_point_reaches_the_triple_point(sw_params, p
     13.17346 GPa lies about 0.3 GPa higher at 1210 K."""
     Pc = float(e2e.coexistence_pressure(phases))
     curves = e2e.dcci_curves(sw_params, [("cd", "bt", 400.0, Pc, inputs.MODE_DCCI_T, 400.0, 1250.0)], seed0=500)
-    ps = [np.interp(1210.0, tp[:, 0], tp[:, 1]) for _, tp in curves.values()]
+    Tt, Pt = e2e.TRIPLE
+    ps = [np.interp(Tt, tp[:, 0], tp[:, 1]) for _, tp in curves.values()]
     print(f"cd/beta-tin from P_coex(400 K) = {Pc:.3f} GPa: P(1210 K) = {np.round(ps, 3)} GPa, "
           f"mean {np.mean(ps):.3f} (paper 9.90(3))", flush=True)
-    assert abs(np.mean(ps) - 9.90) < 0.3
+    assert abs(np.mean(ps) - Pt) < 0.3

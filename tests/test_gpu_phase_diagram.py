@@ -1,5 +1,5 @@
 """The method end to end: the three coexistence lines of Stillinger-Weber
-silicon by dCCI (section 3, section 4.2), from the starting points the paper
+silicon by dCCI (section 3, section 4.3), from the starting points the paper
 computes with absolute free energies, meet at the paper's triple point.
 
 * cd / beta-tin: temperature control, T 400 -> 1250 K over 100 ps from
@@ -38,11 +38,13 @@ from tests import e2e
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-LINES = [  # phase I, phase II, T0 (K), P0 (GPa), mode, schedule start, end
-    ("cd", "bt", 400.0, 13.17346, inputs.MODE_DCCI_T, 400.0, 1250.0),
-    ("cd", "liq", 1689.2, 0.0, inputs.MODE_DCCI_P, 0.0, 10.2),
-    ("bt", "liq", 1365.3, 15.0, inputs.MODE_DCCI_P, 15.0, 9.4),
+_P = e2e.PAPER
+LINES = [  # phase I, phase II, T0 (K), P0 (GPa), mode, schedule start, end (the paper's starting points)
+    ("cd", "bt", 400.0, _P["coexistence_pressure_cd_beta_tin_400K"]["value"], inputs.MODE_DCCI_T, 400.0, 1250.0),
+    ("cd", "liq", _P["melting_point_cd_0GPa"]["value"], 0.0, inputs.MODE_DCCI_P, 0.0, 10.2),
+    ("bt", "liq", _P["melting_point_beta_tin_15GPa"]["value"], 15.0, inputs.MODE_DCCI_P, 15.0, 9.4),
 ]
+T_TP, P_TP = e2e.TRIPLE
 
 
 @pytest.fixture(scope="module")
@@ -58,7 +60,7 @@ def _line(curves, i):
 
 
 def _cd_beta_tin_at_1210(curves):
-    return [np.interp(1210.0, tp[:, 0], tp[:, 1]) for tp in _line(curves, 0)]
+    return [np.interp(T_TP, tp[:, 0], tp[:, 1]) for tp in _line(curves, 0)]
 
 
 def _melting_crossing(curves):
@@ -80,7 +82,7 @@ def _melting_crossing(curves):
 def test_cd_beta_tin_line_passes_the_triple_point(curves):
     ps = _cd_beta_tin_at_1210(curves)
     print(f"cd/beta-tin: P(1210 K) = {np.round(ps, 3)} GPa, mean {np.mean(ps):.3f} (paper 9.90(3))", flush=True)
-    assert abs(np.mean(ps) - 9.90) < 0.3
+    assert abs(np.mean(ps) - P_TP) < 0.3
 
 
 @pytest.mark.parametrize("i", [1, 2])
@@ -88,10 +90,10 @@ def test_melting_lines_reach_the_triple_point(curves, i):
     ts = []
     for tp in _line(curves, i):
         o = np.argsort(tp[:, 1])
-        ts.append(np.interp(9.90, tp[o, 1], tp[o, 0]))
+        ts.append(np.interp(P_TP, tp[o, 1], tp[o, 0]))
     name = "cd/liquid" if i == 1 else "beta-tin/liquid"
     print(f"{name}: T(9.90 GPa) = {np.round(ts, 1)} K, mean {np.mean(ts):.1f} (paper 1210(2))", flush=True)
-    assert abs(np.mean(ts) - 1210.0) < 20.0
+    assert abs(np.mean(ts) - T_TP) < 20.0
 
 
 def test_melting_lines_cross_at_the_triple_point(curves):
@@ -99,7 +101,7 @@ def test_melting_lines_cross_at_the_triple_point(curves):
     of the paper's triple point."""
     Tt, Pt = _melting_crossing(curves)
     print(f"melting lines cross at ({Tt:.1f} K, {Pt:.3f} GPa); paper (1210(2) K, 9.90(3) GPa)", flush=True)
-    assert abs(Tt - 1210.0) < 20.0 and abs(Pt - 9.90) < 0.3
+    assert abs(Tt - T_TP) < 20.0 and abs(Pt - P_TP) < 0.3
 
 
 def test_lines_from_this_builds_own_starting_points_meet_at_the_triple_point(sw_params):
@@ -121,8 +123,8 @@ def test_lines_from_this_builds_own_starting_points_meet_at_the_triple_point(sw_
     print(f"from P_coex(400 K) = {Pc:.3f} GPa, T_m(0) = {Tm['cd_0GPa']:.1f} K, T_m(15 GPa) = "
           f"{Tm['bt_15GPa']:.1f} K: melting lines cross at ({Tt:.1f} K, {Pt:.3f} GPa), cd/beta-tin line at "
           f"{np.mean(ps):.3f} GPa at 1210 K; paper (1210(2) K, 9.90(3) GPa)", flush=True)
-    assert abs(Tt - 1210.0) < 20.0 and abs(Pt - 9.90) < 0.3
-    assert abs(np.mean(ps) - 9.90) < 0.3
+    assert abs(Tt - T_TP) < 20.0 and abs(Pt - P_TP) < 0.3
+    assert abs(np.mean(ps) - P_TP) < 0.3
 
 
 def test_dcci_converges_with_the_switching_time(sw_params):
