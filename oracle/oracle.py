@@ -31,8 +31,8 @@ Contents, each citing the passage of the paper it follows:
                    Gibbs free energy (eq. Gibbs_RS), Einstein free energies.
 
 Readings where the paper is silent (integrator splitting, barostat, noise
-scheme, work discretisation) are the same ones the GPU library implements;
-they are listed with their reasons in the design notes of the repository.
+scheme, work discretisation) are the same ones the GPU library implements,
+each stated at the function that takes it.
 """
 from __future__ import annotations
 
