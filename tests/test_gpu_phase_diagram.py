@@ -18,11 +18,11 @@ paper does not give (equilibration length, barostat parameters).  Measured:
 the melting lines cross at (1210.3 K, 9.93 GPa); the cd/beta-tin line
 passes 1210 K at 10.12 +- 0.02 GPa (six realisations, insensitive to the
 equilibration length and barostat period), 0.2 GPa above the paper's
-crossing: this build's own absolute free energies put P_coex(400 K) at
+crossing: the absolute free energies computed here put P_coex(400 K) at
 13.07 GPa, and an error d in the starting pressure reappears as d T / 400 K
 along the line (the line from 13.07 GPa passes 1210 K at 9.86 GPa).
 
-The same three lines are then run from this build's own starting points
+The same three lines are then run from starting points computed here
 (its absolute free energies: P_coex(400 K), T_m(0 GPa), T_m(15 GPa), from
 the runs shared with the coexistence and melting tests) and must meet at
 the paper's triple point as well.  Measured: from 13.067 GPa, 1684.8 K and
@@ -104,8 +104,8 @@ def test_melting_lines_cross_at_the_triple_point(curves):
     assert abs(Tt - T_TP) < 20.0 and abs(Pt - P_TP) < 0.3
 
 
-def test_lines_from_this_builds_own_starting_points_meet_at_the_triple_point(sw_params):
-    """All three starting points from this build's absolute free energies
+def test_lines_from_the_computed_starting_points_meet_at_the_triple_point(sw_params):
+    """All three starting points from absolute free energies computed here
     (Frenkel-Ladd crystals, the liquid through the Uhlenbeck-Ford fluid),
     then the three dCCI lines from them, two realisations each."""
     import torch
