@@ -744,6 +744,10 @@ struct Fm<double> {
 // Gather batch sizes: list candidates (filter), short-list neighbours in
 // pass 1 and in pass 2 (smaller where the registers are needed elsewhere).
 constexpr int kBatchA = 8;
+// short-list entries pass 1 keeps in LDS (the rest, rarely any, in the
+// global short list): the term loop then reads its neighbour indices without
+// a round trip to memory
+constexpr int kLdsShort = 24;
 template <typename R, bool GRAD>
 struct Batch {
     static constexpr int B = GRAD ? 2 : 4;
@@ -763,6 +767,8 @@ __device__ __forceinline__ int list_entry(const int32_t *list, int k, int n, int
 template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 {
+    extern __shared__ int32_t lsl[];  // [kLdsShort][blockDim.x] short-list entries
+    const int lb = blockDim.x, lt = threadIdx.x;
     constexpr int NV = 20;  // E2, virial 9, dtheta 9, E3
     double acc[NV];
 #pragma unroll
@@ -820,7 +826,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                     dy -= by * rintf(dy * iby);
                     dz -= bz * rintf(dz * ibz);
                     if (k0 + u < cnt && dx * dx + dy * dy + dz * dz < cut2) {
-                        if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = jb[u];
+                        if (nin < kLdsShort) lsl[nin * lb + lt] = jb[u];
+                        else if (nin < kMaxShort) p.sl[(int64_t)nin * N + t] = jb[u];
                         ++nin;
                     }
                 }
@@ -839,7 +846,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         for (int k0 = 0; k0 < ns; k0 += kBatchB) {
             int jb[kBatchB];
 #pragma unroll
-            for (int u = 0; u < kBatchB; ++u) jb[u] = list_entry(p.sl, k0 + u, ns, N, t);
+            for (int u = 0; u < kBatchB; ++u) {
+                const int k = k0 + u < ns ? k0 + u : ns - 1;
+                const int j = k < kLdsShort ? lsl[k * lb + lt] : p.sl[(int64_t)k * N + t];
+                jb[u] = k0 + u < ns ? j : t;
+            }
             double4 xjb[kBatchB];
 #pragma unroll
             for (int u = 0; u < kBatchB; ++u) xjb[u] = p.xs[jb[u]];
@@ -850,10 +861,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
                 const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
                 const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
-                // exact membership; kept entries move down over dropped ones
-                // (an entry is rewritten only after it has been read)
+                // exact membership; the kept entries form the global short
+                // list of pass 2 (an entry of it is rewritten only after it
+                // has been read)
                 if (!(dx * dx + dy * dy + dz * dz < sw.rc2)) continue;
-                if (nkeep != k0 + u) p.sl[(int64_t)nkeep * N + t] = jb[u];
+                p.sl[(int64_t)nkeep * N + t] = jb[u];
                 ++nkeep;
                 const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
                 R r, ri;
@@ -1546,12 +1558,13 @@ hipError_t launch_pass1(const Ctl &c, const DevPtrs &p, const SwParams &sw, int 
                         hipStream_t s)
 {
     const bool g = (c.flags & 1) != 0;
+    const size_t lds = sizeof(int32_t) * kLdsShort * (size_t)block;
     if (mixed) {
-        if (g) hipLaunchKernelGGL((k_pass1<float, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
-        else hipLaunchKernelGGL((k_pass1<float, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+        if (g) hipLaunchKernelGGL((k_pass1<float, true>), tile_grid(c), dim3(block), lds, s, c, p, sw);
+        else hipLaunchKernelGGL((k_pass1<float, false>), tile_grid(c), dim3(block), lds, s, c, p, sw);
     } else {
-        if (g) hipLaunchKernelGGL((k_pass1<double, true>), tile_grid(c), dim3(block), 0, s, c, p, sw);
-        else hipLaunchKernelGGL((k_pass1<double, false>), tile_grid(c), dim3(block), 0, s, c, p, sw);
+        if (g) hipLaunchKernelGGL((k_pass1<double, true>), tile_grid(c), dim3(block), lds, s, c, p, sw);
+        else hipLaunchKernelGGL((k_pass1<double, false>), tile_grid(c), dim3(block), lds, s, c, p, sw);
     }
     if (c.has_uf) {
         if (mixed) hipLaunchKernelGGL((k_uf<float>), tile_grid(c), dim3(block), 0, s, c, p);
