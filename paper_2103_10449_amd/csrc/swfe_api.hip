@@ -55,6 +55,8 @@ struct swfe_ctx {
     swfe_sw_params hsw{};
     Plan plan;
     std::vector<Tile> tiles;
+    std::vector<int32_t> fx_chunk;  // runs of tiles per XCD (empty: in order)
+    int fx_tiles = 0;               // tile count fx_chunk was dealt for
     SwParams sw{};
     int mixed = 0;
     double dt = 0.001;
@@ -299,6 +301,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
 void build_tiles(swfe_ctx *c)
 {
     c->tiles.clear();
+    c->fx_chunk.clear();
     for (Group &g : c->plan.groups) {
         g.tile_begin = (int32_t)c->tiles.size();
         for (int q = 0; q < (g.s1 >= 0 ? 2 : 1); ++q) {
@@ -325,7 +328,6 @@ Ctl make_ctl(const swfe_ctx *c, int in_step, int flags, int force_rebuild)
     k.n_sys = c->n_sys;
     k.n_tiles = (int32_t)c->tiles.size();
     k.n_groups = (int32_t)c->plan.groups.size();
-    k.xcd_stride = (k.n_tiles + 7) / 8;
     k.dt = c->dt;
     k.seed = c->seed;
     k.flags = flags;
@@ -338,7 +340,49 @@ Ctl make_ctl(const swfe_ctx *c, int in_step, int flags, int force_rebuild)
     k.force_rebuild = force_rebuild;
     k.log_every = c->log_every;
     k.log_cap = c->log_cap;
+    const int nc = 8 * kFxChunks;
+    k.fx_len = std::max(1, (k.n_tiles + nc - 1) / nc);
+    const bool costed = (int)c->fx_chunk.size() == nc && c->fx_tiles == k.n_tiles;
+    for (int q = 0; q < nc; ++q) k.fx_chunk[q] = costed ? c->fx_chunk[q] : q;
     return k;
+}
+
+// Runs of tiles dealt to the XCDs by the force passes' cost: an atom costs
+// kFxBase plus its neighbours within rc at the last pass 1 (the gathers of
+// both passes grow with that count, their per-atom streaming does not); the
+// runs go, costliest first, to the XCD with the least cost so far that has
+// fewer than kFxChunks.  Only the placement of blocks changes, never a
+// result.  Synchronises the stream.
+constexpr int64_t kFxBase = 8;
+
+int balance_force_tiles(swfe_ctx *c, hipStream_t s)
+{
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::vector<int32_t> nn((size_t)c->n_total);
+    HIPCHK(c, hipMemcpy(nn.data(), c->ptrs.nnb, nn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int nt = (int)c->tiles.size(), nc = 8 * kFxChunks;
+    const int len = std::max(1, (nt + nc - 1) / nc);
+    std::vector<int64_t> cost(nc, 0);
+    for (int i = 0; i < nt; ++i) {
+        const Tile &t = c->tiles[i];
+        for (int a = 0; a < t.count; ++a)
+            cost[i / len] += kFxBase + std::min(std::max(nn[(size_t)t.start + a], 0), kMaxShort);
+    }
+    std::vector<int> order(nc);
+    for (int q = 0; q < nc; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<int64_t> load(8, 0);
+    std::vector<int> used(8, 0);
+    c->fx_chunk.assign(nc, 0);
+    for (int q : order) {
+        int x = -1;
+        for (int y = 0; y < 8; ++y)
+            if (used[y] < kFxChunks && (x < 0 || load[y] < load[x])) x = y;
+        c->fx_chunk[x * kFxChunks + used[x]++] = q;
+        load[x] += cost[q];
+    }
+    c->fx_tiles = nt;
+    return SWFE_OK;
 }
 
 void drop_graph(swfe_ctx *c)
@@ -567,6 +611,7 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     std::vector<SysState> now;
     RCHK(read_states(ctx, now, s));
     RCHK(take_device_error(ctx, now, s));
+    RCHK(balance_force_tiles(ctx, s));
     ctx->ready = true;
     return SWFE_OK;
 }
@@ -672,7 +717,7 @@ int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *
             // graph is then launched on the caller's stream.
             drop_graph(ctx);
             if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-            HIPCHK(ctx, hipStreamSynchronize(s));
+            RCHK(balance_force_tiles(ctx, s));
             HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
             int rc = enqueue_step(ctx, ctx->cap_stream);
             hipGraph_t g = nullptr;
@@ -789,7 +834,8 @@ int swfe_set_block(swfe_ctx *ctx, int32_t block, void *stream)
     drop_graph(ctx);
     build_tiles(ctx);
     RCHK(upload_tables(ctx, s));
-    return enqueue_forces(ctx, ctx->ptrs, 0, 2, s);
+    RCHK(enqueue_forces(ctx, ctx->ptrs, 0, 2, s));
+    return balance_force_tiles(ctx, s);
 }
 
 int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream)

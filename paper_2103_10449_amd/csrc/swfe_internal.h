@@ -10,6 +10,7 @@ namespace swfe {
 constexpr int kMaxList = 64;       // Verlet-list capacity per atom without UF systems
 constexpr int kMaxListUF = 1024;   // largest capacity a UF reference may ask for
 constexpr int kMaxShort = 48;      // neighbours within rc per atom (pass 1 -> pass 2)
+constexpr int kFxChunks = 4;      // runs of tiles per XCD (block placement)
 constexpr int kSortThreads = 1024; // threads of the per-system sort workgroup
 constexpr int kNumKernels = 9;     // launches of one dynamics step (for profiling)
 constexpr int kRebuildStages = 5;  // rebuild stages
@@ -100,7 +101,7 @@ struct Tile {
 // Global launch parameters.
 struct Ctl {
     int64_t n_total;
-    int32_t n_sys, n_tiles, n_groups, xcd_stride;
+    int32_t n_sys, n_tiles, n_groups, fx_len;  // fx_len: tiles per run (tile placement)
     double dt;
     uint64_t seed;
     int32_t flags;          // PARAM_GRAD / STRAIN
@@ -110,6 +111,9 @@ struct Ctl {
     int32_t in_step;        // 1: the pass belongs to a dynamics step
     int32_t force_rebuild;  // 1: rebuild every system's list now
     int32_t log_every, log_cap;
+    // The tiles are cut into 8 * kFxChunks runs of fx_len tiles; XCD x runs
+    // the runs fx_chunk[x * kFxChunks + j], j < kFxChunks.
+    int32_t fx_chunk[8 * kFxChunks];
 };
 
 struct DevPtrs {

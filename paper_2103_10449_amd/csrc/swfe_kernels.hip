@@ -46,13 +46,19 @@
 namespace swfe {
 
 // ------------------------------------------------------------------ utils --
-// Blocks are dispatched round robin over the 8 XCDs; block b runs tile
-// (b % 8) * stride + b / 8, so each XCD works on a contiguous run of tiles
-// (neighbouring cells) and keeps their data in its own L2.  -1: no tile.
+// Blocks are dispatched round robin over the 8 XCDs, block b to XCD b % 8.
+// The tiles are cut into 8 * kFxChunks runs of fx_len consecutive tiles
+// (neighbouring cells of a system) and XCD x works on the runs
+// fx_chunk[x * kFxChunks + j], so each XCD keeps its runs' data in its own
+// L2 and holds the same number of blocks.  The host deals the runs to the
+// XCDs by cost, because the force passes' work per atom grows with its
+// neighbour count.  -1: no tile.
 __device__ __forceinline__ int tile_of_block(const Ctl &c)
 {
-    const int b = blockIdx.x;
-    const int t = (b & 7) * c.xcd_stride + (b >> 3);
+    const int b = blockIdx.x, x = b & 7, i = b >> 3;
+    const int j = i / c.fx_len;
+    if (j >= kFxChunks) return -1;
+    const int t = c.fx_chunk[x * kFxChunks + j] * c.fx_len + (i - j * c.fx_len);
     return t < c.n_tiles ? t : -1;
 }
 
@@ -1506,7 +1512,7 @@ __global__ void k_clear_err(Ctl c, DevPtrs p)
 }
 
 // ----------------------------------------------------------- launchers -----
-static inline dim3 tile_grid(const Ctl &c) { return dim3(8 * c.xcd_stride); }
+static inline dim3 tile_grid(const Ctl &c) { return dim3(8 * kFxChunks * c.fx_len); }
 
 hipError_t launch_iota(const Ctl &c, const DevPtrs &p, int block, hipStream_t s)
 {
