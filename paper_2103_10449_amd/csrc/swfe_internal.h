@@ -94,6 +94,15 @@ struct SysState {
     int32_t pad;
 };
 
+// Three doubles (24 bytes) for the per-atom vectors that are streamed and
+// never gathered by neighbours; the gathered positions stay double4, one
+// aligned 32-byte record per atom.
+struct dvec3 {
+    double x, y, z;
+};
+
+__host__ __device__ __forceinline__ dvec3 make_dvec3(double x, double y, double z) { return dvec3{x, y, z}; }
+
 struct Tile {
     int32_t sys, start, count, pad;
 };
@@ -122,9 +131,11 @@ struct DevPtrs {
     const double *x0;
     double *e_atom;
     // internal arrays, cell-sorted order
-    double4 *xs, *vs, *fs, *x0s, *xb;     // positions, velocities, F_int, anchors, build positions
-    double4 *txs, *tvs, *tfs, *tx0s;      // permutation staging
-    double4 *zs;                          // normals of the next O step, sorted order
+    double4 *xs;                          // positions
+    dvec3 *vs, *fs, *x0s, *xb;            // velocities, F_int, anchors, build positions
+    double4 *txs;                         // permutation staging
+    dvec3 *tvs, *tfs, *tx0s;
+    dvec3 *zs;                            // normals of the next O step, sorted order
     float4 *xf;                           // FP32 positions wrapped into the box (list filter)
     int32_t *perm, *tperm, *norder, *rank, *cellid;  // norder: staged cell index
     int32_t *cell_count, *cell_start;
@@ -134,7 +145,7 @@ struct DevPtrs {
     void *mom;                            // [n_total][9] moments (v, M) in term precision
     double *e_s;                          // per-atom energy, sorted order
     double *part1, *part2;                // [n_tiles][kNumPart]
-    double4 *fref;                        // UF reference force per atom (UF systems), sorted order
+    dvec3 *fref;                          // UF reference force per atom (UF systems), sorted order
     int32_t *work, *n_work;               // tiles to rebuild in this step, and their count
     double *disp_max;                     // [n_sys][2] max squared displacement since build
                                           // (two slots alternate between steps)

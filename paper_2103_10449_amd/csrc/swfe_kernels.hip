@@ -262,9 +262,9 @@ __global__ void __launch_bounds__(256) k_gather(Ctl c, DevPtrs p, int with_f)
     eff_box(st, box, ibox);
     p.xs[t] = x;
     p.xf[t] = pos_f32(x, box, ibox);
-    p.vs[t] = make_double4(p.v[i], p.v[N + i], p.v[2 * N + i], 0.0);
-    if (with_f) p.fs[t] = make_double4(p.f[i], p.f[N + i], p.f[2 * N + i], 0.0);
-    if (p.x0) p.x0s[t] = make_double4(p.x0[i], p.x0[N + i], p.x0[2 * N + i], 0.0);
+    p.vs[t] = make_dvec3(p.v[i], p.v[N + i], p.v[2 * N + i]);
+    if (with_f) p.fs[t] = make_dvec3(p.f[i], p.f[N + i], p.f[2 * N + i]);
+    if (p.x0) p.x0s[t] = make_dvec3(p.x0[i], p.x0[N + i], p.x0[2 * N + i]);
 }
 
 // Sorted internal arrays -> caller arrays.  what: 1 x and v, 2 f, 4 e_atom,
@@ -279,7 +279,8 @@ __global__ void __launch_bounds__(256) k_scatter(Ctl c, DevPtrs p, int what)
     const int t = tile.start + threadIdx.x;
     const int i = p.perm[t];
     if (what & 1) {
-        const double4 x = p.xs[t], v = p.vs[t];
+        const double4 x = p.xs[t];
+        const dvec3 v = p.vs[t];
         p.x[i] = x.x;
         p.x[N + i] = x.y;
         p.x[2 * N + i] = x.z;
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(256) k_scatter(Ctl c, DevPtrs p, int what)
         p.v[N + i] = v.y;
         p.v[2 * N + i] = v.z;
     }
-    const double4 f = p.fs[t];
+    const dvec3 f = p.fs[t];
     if (what & 2) {
         p.f[i] = f.x;
         p.f[N + i] = f.y;
@@ -329,7 +330,7 @@ __global__ void __launch_bounds__(256) k_fill_noise(Ctl c, DevPtrs p)
     const int t = tile.start + threadIdx.x;
     double z[3];
     normals3(c.seed, d.stream, (uint64_t)p.state[tile.sys].step, (uint64_t)(p.perm[t] - d.off), z);
-    p.zs[t] = make_double4(z[0], z[1], z[2], 0.0);
+    p.zs[t] = make_dvec3(z[0], z[1], z[2]);
 }
 
 // ------------------------------------------------------------- integrate ---
@@ -350,10 +351,10 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
         const int t = tile.start + threadIdx.x;
         double4 x = p.xs[t];
         if (d.mode != MODE_FORCE) {
-            double4 v = p.vs[t];
-            const double4 f = p.fs[t];
-            const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
-            const double4 fr = d.mode == MODE_UF ? p.fref[t] : make_double4(0, 0, 0, 0);
+            dvec3 v = p.vs[t];
+            const dvec3 f = p.fs[t];
+            const dvec3 x0 = d.mode == MODE_FL ? p.x0s[t] : make_dvec3(0, 0, 0);
+            const dvec3 fr = d.mode == MODE_UF ? p.fref[t] : make_dvec3(0, 0, 0);
             const double hdt = 0.5 * c.dt, ka = hdt * d.acc;
             v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, f.x, x.x, x0.x, d.k_spring, fr.x) * st.phi[0];
             v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, f.y, x.y, x0.y, d.k_spring, fr.y) * st.phi[1];
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
             if (o_step_on(d)) {
                 // this step's normals, drawn by the force pass that ended
                 // the previous step (it also formed their mean)
-                const double4 z = p.zs[t];
+                const dvec3 z = p.zs[t];
                 const double c2s = d.c2 * d.sigv;
                 v.x = d.c1 * v.x + c2s * (z.x - st.noise_mean[0]);
                 v.y = d.c1 * v.y + c2s * (z.y - st.noise_mean[1]);
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
             p.xf[t] = pos_f32(x, box, ibox);
         }
         if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z))) atomicOr(&p.state[sys].err, ERR_NONFINITE);
-        const double4 b = p.xb[t];
+        const dvec3 b = p.xb[t];
         const double dx = x.x - b.x * (st.box[0] / st.box_build[0]);
         const double dy = x.y - b.y * (st.box[1] / st.box_build[1]);
         const double dz = x.z - b.z * (st.box[2] / st.box_build[2]);
@@ -530,7 +531,7 @@ __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
         eff_box(p.state[sys], box, ibox);
         p.xs[s] = x;
         p.xf[s] = pos_f32(x, box, ibox);
-        p.xb[s] = x;
+        p.xb[s] = make_dvec3(x.x, x.y, x.z);
         p.vs[s] = p.tvs[i];
         p.fs[s] = p.tfs[i];
         if (p.x0) p.x0s[s] = p.tx0s[i];
@@ -952,7 +953,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         reinterpret_cast<Mom<R> *>(p.mom)[t] = mo;
         if (nin > kMaxShort) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
         p.nnb[t] = nkeep;
-        p.fs[t] = make_double4(F2x, F2y, F2z, 0.0);
+        p.fs[t] = make_dvec3(F2x, F2y, F2z);
         p.e_s[t] = acc[0] + acc[19];
     }
     block_reduce<NV>(acc, p.part1 + (int64_t)ti * kNumPart);
@@ -1008,7 +1009,7 @@ __global__ void __launch_bounds__(256) k_uf(Ctl c, DevPtrs p)
                 e += 0.5 * (double)phi;
             }
         }
-        p.fref[t] = make_double4(fx, fy, fz, 0.0);
+        p.fref[t] = make_dvec3(fx, fy, fz);
     }
     double acc[1] = {e};
     block_reduce<1>(acc, p.part1 + (int64_t)ti * kNumPart + P_UUF);
@@ -1305,11 +1306,11 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
 // noise sums.
 template <int NV>
 __device__ __forceinline__ void next_normals(const Ctl &c, const SysDesc &d, const SysState &st, int t, int atom,
-                                             double4 *zs, double (&acc)[NV])
+                                             dvec3 *zs, double (&acc)[NV])
 {
     double z[3];
     normals3(c.seed, d.stream, (uint64_t)(st.step + c.in_step), (uint64_t)atom, z);
-    zs[t] = make_double4(z[0], z[1], z[2], 0.0);
+    zs[t] = make_dvec3(z[0], z[1], z[2]);
     acc[P_NOISE] = z[0];
     acc[P_NOISE + 1] = z[1];
     acc[P_NOISE + 2] = z[2];
@@ -1338,9 +1339,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const Mom<R> *mom = reinterpret_cast<const Mom<R> *>(p.mom);
         const Mom<R> mA = mom[t];
         // per-atom operands of the tail, in flight during the gather
-        const double4 F2 = p.fs[t];
-        const double4 v0 = p.vs[t];
-        const double4 x0 = d.mode == MODE_FL ? p.x0s[t] : make_double4(0, 0, 0, 0);
+        const dvec3 F2 = p.fs[t];
+        const dvec3 v0 = p.vs[t];
+        const dvec3 x0 = d.mode == MODE_FL ? p.x0s[t] : make_dvec3(0, 0, 0);
         // the first batch of short-list entries loads together with its count
         constexpr int kBatch2 = Batch<R, GRAD>::P2;
         int s0[kBatch2];
@@ -1427,7 +1428,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             acc[16] = hl * gg;  // gamma
             acc[17] = hl * gs;  // sigma
         }
-        double4 F = F2;
+        dvec3 F = F2;
         F.x += F3x;
         F.y += F3y;
         F.z += F3z;
@@ -1438,10 +1439,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             acc[19] = 0.5 * d.k_spring * (ex * ex + ey * ey + ez * ez);
         }
         // final half kick of a dynamics step, then the kinetic energy
-        double4 v = v0;
+        dvec3 v = v0;
         if (c.in_step && d.mode != MODE_FORCE) {
             const double ka = (0.5 * c.dt) * d.acc;
-            const double4 fr = d.mode == MODE_UF ? p.fref[t] : make_double4(0, 0, 0, 0);
+            const dvec3 fr = d.mode == MODE_UF ? p.fref[t] : make_dvec3(0, 0, 0);
             v.x = v.x * st.decay[0] + ka * total_force(d.mode, st.lam, F.x, xa.x, x0.x, d.k_spring, fr.x) * st.phi[0];
             v.y = v.y * st.decay[1] + ka * total_force(d.mode, st.lam, F.y, xa.y, x0.y, d.k_spring, fr.y) * st.phi[1];
             v.z = v.z * st.decay[2] + ka * total_force(d.mode, st.lam, F.z, xa.z, x0.z, d.k_spring, fr.z) * st.phi[2];

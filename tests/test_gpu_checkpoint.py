@@ -65,3 +65,31 @@ def test_checkpoint_of_other_sizes_is_rejected(swfe, sw_params):
     with pytest.raises(swfe.SwfeError):
         b.load_state(blob[:100])
     b.close()
+
+
+def test_autotune_leaves_the_dynamics_where_they_were(swfe, sw_params):
+    """swfe_autotune runs trial steps at every block size and restores the
+    state after each: the run then goes on bitwise like one that only
+    switched to the chosen block size at the same point."""
+    eng = swfe.Engine(copy.deepcopy(_specs()), sw_params, seed=5, precision="mixed")
+    eng.step(60)
+    before = [(eng.positions(k), eng.velocities(k), eng.state()[k]) for k in range(2)]
+    block = eng.autotune()
+    assert block in (64, 128, 256)
+    for k in range(2):
+        x, v, st = before[k]
+        now = eng.state()[k]
+        assert np.array_equal(eng.positions(k), x)
+        assert np.array_equal(eng.velocities(k), v)
+        assert (now["step"], now["sched_k"], now["lam"], now["W"]) == (st["step"], st["sched_k"], st["lam"], st["W"])
+    eng.step(70)
+    got = [(eng.positions(k), eng.state()[k]["W"]) for k in range(2)]
+    eng.close()
+    ref = swfe.Engine(copy.deepcopy(_specs()), sw_params, seed=5, precision="mixed")
+    ref.step(60)
+    ref.set_block(block)
+    ref.step(70)
+    for k in range(2):
+        assert np.array_equal(ref.positions(k), got[k][0])
+        assert ref.state()[k]["W"] == got[k][1]
+    ref.close()
