@@ -42,15 +42,16 @@ SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
 # averaged over the dispatches of a short run of both precisions), each
 # scaled by what the counter reads for a plain 512 MiB device copy:
 # FETCH_SIZE reads half the copied bytes (factor 2.000), WRITE_SIZE all of
-# them (1.000).  The figures hold only for the kernel sources and the host
-# code that places blocks on the XCDs they were taken on (digest).
+# them (1.000).  The figures hold only for the block sizes, the kernel
+# sources and the host code that places blocks on the XCDs they were taken
+# on (digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6282c960f311c98b05d79e715f3a195124bbfa17b70986dd773a6cd9f785aa17",
-    "skin": 1.4, "replicas": 64,
+    "sources_sha256": "f0bf62f1d41d74eb5b4bae958c0ef1f5b8ffb5d0645a8f849326870b5a30978d",
+    "skin": 1.4, "replicas": 64, "block": {"mixed": 128, "fp64": 256},
     "fetch_factor": 2.0, "write_factor": 1.0,
     "kib": {  # (FETCH_SIZE, WRITE_SIZE)
-        ("mixed", "pass1"): (17537.7, 33826.5), ("mixed", "pass2"): (35577.0, 23723.6),
-        ("fp64", "pass1"): (16468.3, 42233.7), ("fp64", "pass2"): (35863.1, 23156.3),
+        ("mixed", "pass1"): (17872.4, 32168.6), ("mixed", "pass2"): (31697.8, 18546.5),
+        ("fp64", "pass1"): (16297.1, 40129.8), ("fp64", "pass2"): (31814.3, 18168.9),
     },
 }
 
@@ -64,13 +65,13 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(name, skin, replicas, precision):
+def measured_traffic(name, skin, replicas, precision, block):
     """HBM bytes per launch of kernel `name`, or None when the counters were
     not taken on this configuration and these kernel sources."""
     m = MEASURED_TRAFFIC
     key = (precision, name)
     if (key not in m["kib"] or skin != m["skin"] or replicas != m["replicas"]
-            or kernel_sources_digest() != m["sources_sha256"]):
+            or block != m["block"][precision] or kernel_sources_digest() != m["sources_sha256"]):
         return None
     fetch, write = m["kib"][key]
     return 1024.0 * (fetch * m["fetch_factor"] + write * m["write_factor"])
@@ -84,7 +85,7 @@ def kernel_flops(name, n_atoms, ordered_pairs):
     return None
 
 
-def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, skins=None):
+def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, skins=None, block=0):
     import torch
     from paper_2103_10449_amd import swfe
 
@@ -93,7 +94,10 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
     specs = copy.deepcopy(wl.systems)
     n_atoms = sum(s.n for s in specs)
     eng = swfe.Engine(specs, P, dt=wl.dt, seed=seed, precision=precision)
-    block = eng.autotune()
+    if block:
+        eng.set_block(block)
+    else:
+        block = eng.autotune()
     print(f"# {precision}: engine ready, block {block}", file=sys.stderr, flush=True)
     starts = [(s.sched_start, s.sched_end) for s in specs]
     # warm-up at the start of the path (lambda held); its first steps pick
@@ -279,6 +283,10 @@ def main():
     ap.add_argument("--no-per-config", action="store_true",
                     help="skip the per-configuration rates of the smaller workloads")
     ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--block", type=int, default=0, choices=(0, 64, 128, 256),
+                    help="block size of the mixed-precision run (0: swfe_autotune)")
+    ap.add_argument("--block-fp64", type=int, default=0, choices=(0, 64, 128, 256),
+                    help="block size of the FP64 run (0: swfe_autotune)")
     ap.add_argument("--skin", type=float, default=1.4,
                     help="Verlet skin in A (default 1.4, the fastest of 0.4-1.8 A on this workload; "
                          "0: choose among 0.4, 0.7, 1.0, 1.4 A by timing during warm-up)")
@@ -316,12 +324,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     skins = (args.skin,) if args.skin > 0 else None
-    mixed = run_precision("mixed", builder, steps, args.warmup, P, seed, args.profile_steps, skins)
+    mixed = run_precision("mixed", builder, steps, args.warmup, P, seed, args.profile_steps, skins, args.block)
     print(f"# mixed: {mixed['n_atoms']} atoms, {mixed['steps']} steps in {mixed['wall']:.3f} s "
           f"(block {mixed['block']}, {mixed['pairs'] / mixed['n_atoms']:.2f} neighbours/atom)", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_precision("fp64", builder, steps, args.warmup, P, seed, args.profile_steps, skins)
+        fp64 = run_precision("fp64", builder, steps, args.warmup, P, seed, args.profile_steps, skins, args.block_fp64)
         print(f"# fp64: {fp64['steps']} steps in {fp64['wall']:.3f} s", file=sys.stderr, flush=True)
 
     value = mixed["n_atoms"] * mixed["steps"] / mixed["wall"]
@@ -362,7 +370,7 @@ def main():
         avg = prof[name] / n_prof / 1e3              # s per launch
         fl = kernel_flops(name, mixed["n_atoms"], mixed["pairs"])
         ach = fl / avg / 1e12 if fl else None
-        traffic = measured_traffic(name, mixed["skin"], args.replicas, "mixed")
+        traffic = measured_traffic(name, mixed["skin"], args.replicas, "mixed", mixed["block"])
         out["roofline"] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": PEAK["mixed"] / 1e12,
                            "unit": "TFLOP/s", "frac": (ach / (PEAK["mixed"] / 1e12)) if ach else None,
                            "traffic": traffic, "avg_launch_us": 1e6 * avg,
@@ -373,7 +381,7 @@ def main():
             p64 = fp64["prof"]
             avg64 = p64[name] / n_prof / 1e3
             fl64 = kernel_flops(name, fp64["n_atoms"], fp64["pairs"])
-            tr64 = measured_traffic(name, fp64["skin"], args.replicas, "fp64")
+            tr64 = measured_traffic(name, fp64["skin"], args.replicas, "fp64", fp64["block"])
             out["roofline_fp64"] = {"kernel": name, "achieved": fl64 / avg64 / 1e12, "peak": PEAK["fp64"] / 1e12,
                                     "frac": fl64 / avg64 / PEAK["fp64"], "traffic": tr64,
                                     "avg_launch_us": 1e6 * avg64,
