@@ -141,7 +141,7 @@ struct DevPtrs {
     int32_t *cell_count, *cell_start;
     int32_t *nl, *nl_cnt;                 // Verlet list of sorted positions (layouts at list_put)
     int32_t *nnb;                         // neighbours within rc per atom (last pass 1)
-    int32_t *sl;                          // [kMaxShort][n_total] those neighbours (sorted positions)
+    int32_t *sl;                          // those neighbours, in the Verlet list's entry format (list_put)
     void *mom;                            // [n_total][9] moments (v, M) in term precision
     double *e_s;                          // per-atom energy, sorted order
     double *part1, *part2;                // [n_tiles][kNumPart]

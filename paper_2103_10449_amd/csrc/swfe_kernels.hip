@@ -761,16 +761,6 @@ struct Batch {
     static constexpr int P2 = sizeof(R) == 4 ? 4 : 2;
 };
 
-// Entry k of atom t's short list ([row][n_total] layout, n valid rows, n >= 1).
-// Rows past the end read the last valid row (no branch around the load) and
-// yield t itself, whose position is always valid to load.
-__device__ __forceinline__ int list_entry(const int32_t *list, int k, int n, int64_t N, int t)
-{
-    const int row = k < n ? k : n - 1;
-    const int j = list[(int64_t)row * N + t];
-    return k < n ? j : t;
-}
-
 template <typename R, bool GRAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
 {
@@ -869,10 +859,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
                 const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
                 // exact membership; the kept entries form the global short
-                // list of pass 2 (an entry of it is rewritten only after it
-                // has been read)
+                // list of pass 2, in the Verlet list's entry format (16-bit
+                // entries fill words 0 .. kMaxShort/2 - 1, below the rows
+                // from kLdsShort on that this loop still reads; 32-bit
+                // entries rewrite a row only after it has been read)
                 if (!(dx * dx + dy * dy + dz * dz < sw.rc2)) continue;
-                p.sl[(int64_t)nkeep * N + t] = jb[u];
+                list_put(c, p.sl, nkeep, N, t, jb[u], off);
                 ++nkeep;
                 const R ddx = (R)dx, ddy = (R)dy, ddz = (R)dz;
                 R r, ri;
@@ -1344,9 +1336,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const dvec3 x0 = d.mode == MODE_FL ? p.x0s[t] : make_dvec3(0, 0, 0);
         // the first batch of short-list entries loads together with its count
         constexpr int kBatch2 = Batch<R, GRAD>::P2;
-        int s0[kBatch2];
-#pragma unroll
-        for (int u = 0; u < kBatch2; ++u) s0[u] = p.sl[(int64_t)u * N + t];
+        uint32_t s0[kBatch2];
+        list_load<kBatch2>(c, p.sl, 0, kMaxShort, N, t, s0);
         const int cnt = p.nnb[t];
         const int atom = p.perm[t] - d.off;
         // normals of the next O step (stored for it, and summed for its
@@ -1361,13 +1352,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // batches whose indices, positions and moments are loaded together
         for (int k0 = 0; k0 < cnt; k0 += kBatch2) {
             int jb[kBatch2];
-            if (k0 == 0) {
-#pragma unroll
-                for (int u = 0; u < kBatch2; ++u) jb[u] = u < cnt ? s0[u] : t;
-            } else {
-#pragma unroll
-                for (int u = 0; u < kBatch2; ++u) jb[u] = list_entry(p.sl, k0 + u, cnt, N, t);
-            }
+            if (k0 == 0) list_decode<kBatch2>(c, s0, 0, cnt, t, (int)d.off, jb);
+            else list_batch<kBatch2>(c, p.sl, k0, cnt, N, t, (int)d.off, jb);
             double4 xjb[kBatch2];
             Mom<R> mjb[kBatch2];
 #pragma unroll
