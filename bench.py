@@ -46,12 +46,12 @@ SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
 # sources and the host code that places blocks on the XCDs they were taken
 # on (digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "f0bf62f1d41d74eb5b4bae958c0ef1f5b8ffb5d0645a8f849326870b5a30978d",
+    "sources_sha256": "3b8592c28d00042e40b74b88e9e45fe25b4709ed567907280a360994f902566b",
     "skin": 1.4, "replicas": 64, "block": {"mixed": 128, "fp64": 256},
     "fetch_factor": 2.0, "write_factor": 1.0,
     "kib": {  # (FETCH_SIZE, WRITE_SIZE)
-        ("mixed", "pass1"): (17872.4, 32168.6), ("mixed", "pass2"): (31697.8, 18546.5),
-        ("fp64", "pass1"): (16297.1, 40129.8), ("fp64", "pass2"): (31814.3, 18168.9),
+        ("mixed", "pass1"): (17774.3, 25538.8), ("mixed", "pass2"): (28159.2, 18587.6),
+        ("fp64", "pass1"): (16166.7, 34012.5), ("fp64", "pass2"): (28312.5, 18166.5),
     },
 }
 
