@@ -166,6 +166,33 @@ def test_system_above_16bit_list_indices(swfe, sw_params, prec, ftol):
     alone.close()
 
 
+def _fcc_dense():
+    """Compressed fcc (a = 3.0 A, 108 atoms): 37-42 neighbours within rc per
+    atom, so pass 1's filter fills its 24 on-chip slots per atom and goes on
+    in the global rows, while the exact list for pass 2 is written beside
+    them."""
+    xl, box = inputs.fcc((3, 3, 3), 3.0)
+    return spec(inputs.perturb(xl, 0.03, inputs.rng(705, 0, 0)), box)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("block", [64, 256])
+def test_dense_neighbourhoods_past_the_on_chip_short_list(swfe, sw_params, prec, block):
+    s = _fcc_dense()
+    print(f"dense fcc {prec} block {block} N={s.n}", flush=True)
+    eng = swfe.Engine([s], sw_params, precision=prec, block=block)
+    out = eng.compute_forces().cpu().numpy()[0]
+    _, most, _ = eng.neighbor_stats()
+    ref = orc.sw_eval(s.x, s.box, sw_params)
+    assert most > 24
+    # the net forces are small against the cancelling pair and triplet
+    # contributions (~45 eV/atom of repulsion), which sets the mixed bar
+    tol_f, tol_e = (1e-10, 1e-12) if prec == "fp64" else (1e-4, 1e-6)
+    assert force_err(eng.forces(0), ref["F"]) < tol_f
+    assert out[0] == pytest.approx(ref["E"], rel=tol_e)
+    eng.close()
+
+
 def test_neighbour_overflow_is_reported(swfe, sw_params):
     """More than 32 atoms within the cutoff of an atom: the kernel caps the
     list and the library reports SWFE_E_OVERFLOW."""
