@@ -33,11 +33,17 @@ C_PAIR = 56     # SW two-body energy, force and virial per unordered pair
 C_MOM = 29      # g(r) and the 11 three-body moments per (centre, neighbour)
 C_D3 = 95       # three-body force/virial contribution per (centre, neighbour)
 C_ATOM2 = 50    # per atom in pass 2: own three-body energy, Einstein, kick, kinetic energy
+# Algorithmic HBM bytes of one integrate launch per atom: position and
+# velocity read and written (4 x 24), force, stored normals and build position
+# read (3 x 24), FP32 position written (12); Frenkel-Ladd atoms also read
+# their anchor (24).
+INTEGRATE_BYTES = 180
+INTEGRATE_BYTES_FL = 24
 PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
 PEAK_HBM = 8.0e12                             # B/s
 SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
 
-# HBM bytes per launch of the force passes on this workload (64 replicas,
+# HBM bytes per launch of the force passes and integrate on this workload (64 replicas,
 # skin 1.4 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
 # averaged over the dispatches of a short run of both precisions), each
 # scaled by what the counter reads for a plain 512 MiB device copy:
@@ -52,6 +58,7 @@ MEASURED_TRAFFIC = {
     "kib": {  # (FETCH_SIZE, WRITE_SIZE)
         ("mixed", "pass1"): (17774.3, 25538.8), ("mixed", "pass2"): (28159.2, 18587.6),
         ("fp64", "pass1"): (16166.7, 34012.5), ("fp64", "pass2"): (28312.5, 18166.5),
+        ("mixed", "integrate"): (18147.7, 18217.4),
     },
 }
 
@@ -388,6 +395,15 @@ def main():
                                     "hbm_GBps": tr64 / avg64 / 1e9 if tr64 else None,
                                     "hbm_frac": tr64 / avg64 / PEAK_HBM if tr64 else None,
                                     "per_kernel_us": {k: 1e3 * v / n_prof for k, v in p64.items()}}
+        if "integrate" in prof:
+            # the step's streaming kernel, against the HBM roof
+            avg_i = prof["integrate"] / n_prof / 1e3
+            n_fl = sum(s.n for s in base.systems if s.mode == inputs.MODE_FL)
+            alg = INTEGRATE_BYTES * mixed["n_atoms"] + INTEGRATE_BYTES_FL * n_fl
+            tr_i = measured_traffic("integrate", mixed["skin"], args.replicas, "mixed", mixed["block"])
+            out["roofline_integrate"] = {"bound": "hbm", "kernel": "integrate", "achieved": alg / avg_i / 1e9,
+                                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": alg / avg_i / PEAK_HBM,
+                                         "algorithmic_bytes": alg, "traffic": tr_i, "avg_launch_us": 1e6 * avg_i}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     if not args.no_per_config:
