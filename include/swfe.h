@@ -182,7 +182,7 @@ int swfe_workspace_bytes(const swfe_system_desc *d, int32_t n_sys, const swfe_sw
  * 0 of the thermostat noise; dt in ps; precision SWFE_PREC_*.  Each system's
  * schedule starts at step 0 (lambda, P_S from sched_start).  Velocities must
  * carry zero total momentum per system for the fixed centre of mass the
- * zero-sum noise maintains.  Synchronises the stream once. */
+ * zero-sum noise maintains.  Synchronises the stream. */
 int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys,
                      const swfe_sw_params *p, const swfe_buffers *b, uint64_t seed, double dt,
                      int32_t precision, void *stream);
