@@ -170,7 +170,7 @@ typedef struct {
  * releases captured graphs); NULL is ignored. */
 int swfe_create(swfe_ctx **out);
 void swfe_destroy(swfe_ctx *ctx);
-const char *swfe_last_error(const swfe_ctx *ctx);
+const char *swfe_last_error(const swfe_ctx *ctx);  /* NULL: last context-free call */
 
 /* Bytes of device workspace needed for these systems.  Checks descriptors
  * (SWFE_E_INVALID_ARG, SWFE_E_BOX_TOO_SMALL) without touching the GPU. */
@@ -178,22 +178,31 @@ int swfe_workspace_bytes(const swfe_system_desc *d, int32_t n_sys, const swfe_sw
                          size_t *bytes);
 
 /* Set up n_sys systems on the caller's buffers (host descriptors, device
- * buffers), then evaluate the initial interaction.  seed is Philox key word
- * 0 of the thermostat noise; dt in ps; precision SWFE_PREC_*.  Each system's
- * schedule starts at step 0 (lambda, P_S from sched_start).  Velocities must
+ * buffers), then evaluate the initial interaction.  The systems are the
+ * switched Hamiltonians of section 2 (H_lambda of section 2.1 for
+ * Frenkel-Ladd, eq. H_RS with P_S = lambda P of eq. P_sc for reversible
+ * scaling, the pressure ramp of eq. Wmech_dyn) and the coupled phases of
+ * section 3.  seed is Philox key word 0 of the thermostat noise; dt in ps;
+ * precision SWFE_PREC_*.  Each system's schedule starts at step 0 (lambda,
+ * P_S from sched_start).  Velocities must
  * carry zero total momentum per system for the fixed centre of mass the
  * zero-sum noise maintains.  Synchronises the stream. */
 int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys,
                      const swfe_sw_params *p, const swfe_buffers *b, uint64_t seed, double dt,
                      int32_t precision, void *stream);
 
-/* Neighbour build at the current positions (step a1): cell index per atom,
+/* Neighbour build at the current positions: cell index per atom,
  * deterministic counting sort by cell (ties in atom order), and the Verlet
- * lists of every system. */
+ * lists of every system within the Stillinger-Weber cutoff a sigma plus the
+ * skin.  The paper's molecular dynamics (section 4) finds its interacting
+ * pairs this way implicitly; both potential terms vanish beyond a sigma. */
 int swfe_build_neighbors(swfe_ctx *ctx, void *stream);
 
-/* Interaction at the current positions: binning, pair terms and three-body
- * moments, force gather, per-system reductions.  Writes f (and e_atom).
+/* Interaction at the current positions: the Stillinger-Weber energy of the
+ * paper's silicon (section 4; the two-body and three-body terms of the
+ * parameter block above), its forces, virial and parameter gradient --
+ * binning, pair terms and three-body moments, force gather, per-system
+ * reductions.  Writes f (and e_atom).
  * flags: SWFE_PARAM_GRAD, SWFE_STRAIN.  strain: host [n_sys][9] diagonal
  * strains (off-diagonal entries must be 0) used with SWFE_STRAIN, else NULL.
  * grad_scale: device [n_sys] upstream gradient dL/dE or NULL (=1).
@@ -214,18 +223,26 @@ int swfe_set_params(swfe_ctx *ctx, const swfe_sw_params *p);
  * work accumulators of every system.  Does not synchronise. */
 int swfe_set_schedule(swfe_ctx *ctx, const swfe_system_desc *d, void *stream);
 
-/* Advance every system by n_steps of switched dynamics (steps a4-a9):
- * switch lambda and accumulate work, barostat half step, B A O A kick/drift/
- * Langevin, interaction, B, barostat half step.  dCCI pairs update their
+/* Advance every system by n_steps of switched dynamics: switch lambda (and
+ * P_S) on its schedule and accumulate the work increment of eq. Wdyn
+ * (discretised as H(lambda_{k+1}) - H(lambda_k) at the current microstate;
+ * eqs. Wrev_HI, Wdyn_RS, Wmech_dyn for the modes), barostat half step,
+ * B A O A kick/drift/Langevin (the Langevin thermostat and barostat of
+ * section 4.1), interaction, B, barostat half step.  dCCI pairs update their
  * shared lambda and P_S from both phases' instantaneous per-atom energy and
- * volume.  use_graph != 0 replays one captured step graph.  Errors raised
+ * volume (section 3, eqs. Ps_coex_discreted and l_coex_discreted).  After a
+ * SWFE_STRAIN force evaluation the interaction is first evaluated again at
+ * the unstrained positions (f is overwritten).  use_graph != 0 replays one captured step graph.  Errors raised
  * on the device (overflow, non-finite, dCCI singular, box too small) are
  * reported by the next synchronising call. */
 int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *stream);
 
 /* Synchronise and copy per-system work W (eV), lambda, P_S (GPa) and the
- * schedule step to host arrays of n_sys entries (any may be NULL).  Returns
- * the first pending device error as a status code. */
+ * schedule step to host arrays of n_sys entries (any may be NULL).  W is the
+ * dynamical work of eq. Wdyn accumulated since the schedule was installed;
+ * a forward and a backward run give Delta F = (W_fwd - W_bwd)/2 (eq. dF)
+ * and the dissipated heat (eq. Qdiss).  Returns the first pending device
+ * error as a status code (the arrays are filled either way). */
 int swfe_work_integral(swfe_ctx *ctx, double *W, double *lam, double *Ps, int64_t *steps,
                        void *stream);
 

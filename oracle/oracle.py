@@ -71,7 +71,7 @@ def build(force: bool = True) -> str:
     src = os.path.join(_HERE, "sw_oracle.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -98,8 +98,17 @@ def _load():
                                     ctypes.c_int, dp, dp, dp, dp]
         lib.orc_uf_eval.restype = ctypes.c_int
         lib.orc_einstein.restype = ctypes.c_double
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the neighbour search (default 1).  Each atom's neighbours
+    are found independently and listed in the same order for any count, so
+    no result depends on it; it only shortens large evaluations."""
+    _load().orc_set_threads(int(n))
 
 
 def _ptr(a: Optional[np.ndarray]):

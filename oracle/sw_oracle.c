@@ -65,11 +65,56 @@ static double perp_width(const double h[9], int k)
     return vol / sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
 }
 
+/* Threads of the neighbour search (1 unless a caller asks for more).  Every
+ * atom's list is built independently and in the same order whatever the
+ * count, so results do not depend on it. */
+static int orc_threads = 1;
+
+void orc_set_threads(int n) { orc_threads = n > 0 ? n : 1; }
+
+/*
+ * The neighbours (j, image) of atom i with |r_j + image - r_i| < rc, in the
+ * order j, then image.  Writes them to out (when not NULL) and returns their
+ * count.
+ */
+static int atom_neighbours(int i, int n, const double* x, const double h[9], const double hinv[9],
+                           const int m[3], double rc2, orc_nb_t* out)
+{
+    int cnt = 0;
+    for (int j = 0; j < n; ++j) {
+        double d0[3], s[3];
+        for (int a = 0; a < 3; ++a) d0[a] = x[3 * j + a] - x[3 * i + a];
+        for (int a = 0; a < 3; ++a)
+            s[a] = hinv[a * 3 + 0] * d0[0] + hinv[a * 3 + 1] * d0[1] + hinv[a * 3 + 2] * d0[2];
+        for (int a = 0; a < 3; ++a) s[a] -= round(s[a]);
+        for (int i0 = -m[0]; i0 <= m[0]; ++i0)
+            for (int i1 = -m[1]; i1 <= m[1]; ++i1)
+                for (int i2 = -m[2]; i2 <= m[2]; ++i2) {
+                    double t[3] = {s[0] + i0, s[1] + i1, s[2] + i2};
+                    double d[3];
+                    for (int a = 0; a < 3; ++a)
+                        d[a] = h[a * 3 + 0] * t[0] + h[a * 3 + 1] * t[1] + h[a * 3 + 2] * t[2];
+                    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    if (r2 >= rc2) continue;
+                    if (j == i && i0 == 0 && i1 == 0 && i2 == 0) continue;
+                    if (r2 == 0.0) continue;
+                    if (out) {
+                        out[cnt].j = j;
+                        for (int a = 0; a < 3; ++a) out[cnt].d[a] = d[a];
+                        out[cnt].r = sqrt(r2);
+                    }
+                    ++cnt;
+                }
+    }
+    return cnt;
+}
+
 /*
  * Build, for every atom i, the list of (j, image) with |r_j + image - r_i| < rc.
  * x is [n][3]; h is the 3x3 cell matrix (row a, column b = component a of box
  * vector b).  force_images != 0 selects the explicit-image sum even for large
- * cells.  Returns 0, or -1 on allocation failure.
+ * cells.  The lists are counted first, then written at their offsets.
+ * Returns 0, or -1 on allocation failure.
  */
 static int neighbours(int n, const double* x, const double h[9], double rc, int force_images,
                       int** start_out, orc_nb_t** list_out)
@@ -85,44 +130,17 @@ static int neighbours(int n, const double* x, const double h[9], double rc, int 
     }
     if (!use_images) m[0] = m[1] = m[2] = 0;
 
-    int cap = 64 * (n > 0 ? n : 1), cnt = 0;
-    orc_nb_t* list = (orc_nb_t*)malloc(sizeof(orc_nb_t) * cap);
     int* start = (int*)malloc(sizeof(int) * (n + 1));
-    if (!list || !start) { free(list); free(start); return -1; }
-    double rc2 = rc * rc;
-    for (int i = 0; i < n; ++i) {
-        start[i] = cnt;
-        for (int j = 0; j < n; ++j) {
-            double d0[3], s[3];
-            for (int a = 0; a < 3; ++a) d0[a] = x[3 * j + a] - x[3 * i + a];
-            for (int a = 0; a < 3; ++a)
-                s[a] = hinv[a * 3 + 0] * d0[0] + hinv[a * 3 + 1] * d0[1] + hinv[a * 3 + 2] * d0[2];
-            for (int a = 0; a < 3; ++a) s[a] -= round(s[a]);
-            for (int i0 = -m[0]; i0 <= m[0]; ++i0)
-                for (int i1 = -m[1]; i1 <= m[1]; ++i1)
-                    for (int i2 = -m[2]; i2 <= m[2]; ++i2) {
-                        double t[3] = {s[0] + i0, s[1] + i1, s[2] + i2};
-                        double d[3];
-                        for (int a = 0; a < 3; ++a)
-                            d[a] = h[a * 3 + 0] * t[0] + h[a * 3 + 1] * t[1] + h[a * 3 + 2] * t[2];
-                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                        if (r2 >= rc2) continue;
-                        if (j == i && i0 == 0 && i1 == 0 && i2 == 0) continue;
-                        if (r2 == 0.0) continue;
-                        if (cnt == cap) {
-                            cap *= 2;
-                            orc_nb_t* nl = (orc_nb_t*)realloc(list, sizeof(orc_nb_t) * cap);
-                            if (!nl) { free(list); free(start); return -1; }
-                            list = nl;
-                        }
-                        list[cnt].j = j;
-                        for (int a = 0; a < 3; ++a) list[cnt].d[a] = d[a];
-                        list[cnt].r = sqrt(r2);
-                        ++cnt;
-                    }
-        }
-    }
-    start[n] = cnt;
+    if (!start) return -1;
+    const double rc2 = rc * rc;
+#pragma omp parallel for num_threads(orc_threads) schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) start[i + 1] = atom_neighbours(i, n, x, h, hinv, m, rc2, NULL);
+    start[0] = 0;
+    for (int i = 0; i < n; ++i) start[i + 1] += start[i];
+    orc_nb_t* list = (orc_nb_t*)malloc(sizeof(orc_nb_t) * (start[n] > 0 ? start[n] : 1));
+    if (!list) { free(start); return -1; }
+#pragma omp parallel for num_threads(orc_threads) schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) atom_neighbours(i, n, x, h, hinv, m, rc2, list + start[i]);
     *start_out = start;
     *list_out = list;
     return 0;

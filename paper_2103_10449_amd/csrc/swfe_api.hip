@@ -70,21 +70,37 @@ struct swfe_ctx {
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
     hipStream_t cap_stream = nullptr;  // library-owned stream used only for capture
+    // the last force evaluation was strained: forces, energies and virial
+    // belong to the strained box until the interaction is evaluated again
+    bool forces_stale = false;
 };
 
 namespace {
 
-int fail(swfe_ctx *c, int code, const std::string &msg)
+// Message of the last failing call without a context (swfe_workspace_bytes),
+// returned by swfe_last_error(NULL).  A fixed buffer:
+// recording it allocates nothing.
+char g_free_err[256] = "";
+
+int fail(swfe_ctx *c, int code, const char *msg)
 {
-    if (c) c->err = msg;
+    if (c) {
+        c->err = msg;
+    } else {
+        strncpy(g_free_err, msg, sizeof g_free_err - 1);
+        g_free_err[sizeof g_free_err - 1] = '\0';
+    }
     return code;
 }
 
-#define HIPCHK(ctx, expr)                                                                 \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(ctx, SWFE_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+#define HIPCHK(ctx, expr)                                                         \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            char m_[256];                                                         \
+            snprintf(m_, sizeof m_, "%s: %s", #expr, hipGetErrorString(e_));      \
+            return fail(ctx, SWFE_E_HIP, m_);                                     \
+        }                                                                         \
     } while (0)
 
 #define RCHK(expr)              \
@@ -118,10 +134,12 @@ SwParams make_sw(const swfe_sw_params &p)
     return s;
 }
 
-// Validate descriptors; compute the device descriptors, the reduction groups
-// and the workspace layout.  Does not touch the GPU.
-int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw_params *p, double dt,
-                 double skin, Plan &out)
+// Validate descriptors; compute the device descriptors (desc[n_sys]), the
+// reduction groups (groups[n_sys] of capacity, *n_groups used) and the
+// workspace layout.  Writes only into the given arrays and P's scalars (no
+// allocation); does not touch the GPU.
+int plan_core(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw_params *p, double dt,
+              double skin, SysDesc *desc, Group *groups, int *n_groups, Plan &P)
 {
     if (!d || !p || n_sys <= 0) return fail(ctx, SWFE_E_INVALID_ARG, "null descriptor/params or n_sys <= 0");
     if (!(p->a > 0 && p->sigma > 0 && p->mass > 0))
@@ -129,7 +147,7 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     if (!(dt > 0)) return fail(ctx, SWFE_E_INVALID_ARG, "dt must be > 0");
     if (!(skin >= 0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be >= 0");
     const double rc = p->a * p->sigma;
-    Plan P;
+    P.list_cap = kMaxList;
     int64_t off = 0, tiles = 0, cells = 0;
     for (int s = 0; s < n_sys; ++s) {
         const swfe_system_desc &q = d[s];
@@ -225,11 +243,12 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
         sd.s_start = q.sched_start;
         sd.s_end = q.sched_end;
         sd.s_steps = q.sched_steps;
-        P.desc.push_back(sd);
+        desc[s] = sd;
         tiles += (q.n_atoms + 63) / 64;
         off += q.n_atoms;
     }
     if (off >= ((int64_t)1 << 31) / P.list_cap) return fail(ctx, SWFE_E_INVALID_ARG, "too many atoms");
+    int ng = 0;
     for (int s = 0; s < n_sys; ++s) {
         Group g{};
         if (is_dcci(d[s].mode)) {
@@ -240,10 +259,11 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
             g.s0 = s;
             g.s1 = -1;
         }
-        P.desc[g.s0].group = (int32_t)P.groups.size();
-        if (g.s1 >= 0) P.desc[g.s1].group = (int32_t)P.groups.size();
-        P.groups.push_back(g);
+        desc[g.s0].group = ng;
+        if (g.s1 >= 0) desc[g.s1].group = ng;
+        groups[ng++] = g;
     }
+    *n_groups = ng;
     P.n_total = off;
     P.cells = cells;
     P.max_tiles = tiles;
@@ -288,63 +308,160 @@ int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe
     L.desc = take(sizeof(SysDesc) * n_sys);
     L.state = take(sizeof(SysState) * n_sys);
     L.tiles = take(sizeof(Tile) * (size_t)tiles);
-    L.groups = take(sizeof(Group) * P.groups.size());
+    L.groups = take(sizeof(Group) * (size_t)ng);
     L.log = take(8 * (size_t)kLogCapMax * SWFE_LOG_STRIDE);
     L.strain = take(8 * 3 * (size_t)n_sys);
     L.total = o;
+    return SWFE_OK;
+}
+
+int plan_systems(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw_params *p, double dt,
+                 double skin, Plan &out)
+{
+    if (!d || !p || n_sys <= 0) return fail(ctx, SWFE_E_INVALID_ARG, "null descriptor/params or n_sys <= 0");
+    Plan P;
+    P.desc.resize(n_sys);
+    P.groups.resize(n_sys);
+    int ng = 0;
+    RCHK(plan_core(ctx, d, n_sys, p, dt, skin, P.desc.data(), P.groups.data(), &ng, P));
+    P.groups.resize(ng);
     out = std::move(P);
     return SWFE_OK;
 }
 
 // Tiles of `block` atoms, laid out group by group so that the tiles of a
-// group (a system, or both phases of a dCCI pair) are contiguous.
-void build_tiles(swfe_ctx *c)
+// group (a system, or both phases of a dCCI pair) are contiguous.  Writes at
+// most cap tiles into out and returns their count, or -1 when more are
+// needed.  Sets the tile ranges of the descriptors and groups.
+int fill_tiles(SysDesc *desc, Group *groups, int n_groups, int block, Tile *out, int cap)
 {
-    c->tiles.clear();
-    c->fx_chunk.clear();
-    for (Group &g : c->plan.groups) {
-        g.tile_begin = (int32_t)c->tiles.size();
+    int nt = 0;
+    for (int gi = 0; gi < n_groups; ++gi) {
+        Group &g = groups[gi];
+        g.tile_begin = nt;
         for (int q = 0; q < (g.s1 >= 0 ? 2 : 1); ++q) {
             const int s = q == 0 ? g.s0 : g.s1;
-            SysDesc &d = c->plan.desc[s];
-            d.tile_begin = (int32_t)c->tiles.size();
-            for (int64_t a = 0; a < d.n; a += c->block) {
+            SysDesc &d = desc[s];
+            d.tile_begin = nt;
+            for (int64_t a = 0; a < d.n; a += block) {
+                if (nt >= cap) return -1;
                 Tile t{};
                 t.sys = s;
                 t.start = (int32_t)(d.off + a);
-                t.count = (int32_t)std::min<int64_t>(c->block, d.n - a);
-                c->tiles.push_back(t);
+                t.count = (int32_t)std::min<int64_t>(block, d.n - a);
+                out[nt++] = t;
             }
-            d.tile_end = (int32_t)c->tiles.size();
+            d.tile_end = nt;
         }
-        g.tile_end = (int32_t)c->tiles.size();
+        g.tile_end = nt;
     }
+    return nt;
+}
+
+void build_tiles(swfe_ctx *c)
+{
+    c->fx_chunk.clear();
+    // tiles at the smallest block size bound the count at every size
+    c->tiles.resize((size_t)c->plan.max_tiles);
+    const int nt = fill_tiles(c->plan.desc.data(), c->plan.groups.data(), (int)c->plan.groups.size(), c->block,
+                              c->tiles.data(), (int)c->tiles.size());
+    c->tiles.resize((size_t)std::max(nt, 0));
+}
+
+// Device pointers of the workspace parts at base w.
+void carve(DevPtrs &q, char *w, const Layout &L)
+{
+    q.xs = (double4 *)(w + L.xs);
+    q.vs = (dvec3 *)(w + L.vs);
+    q.fs = (dvec3 *)(w + L.fs);
+    q.x0s = (dvec3 *)(w + L.x0s);
+    q.xb = (dvec3 *)(w + L.xb);
+    q.txs = (double4 *)(w + L.txs);
+    q.tvs = (dvec3 *)(w + L.tvs);
+    q.tfs = (dvec3 *)(w + L.tfs);
+    q.tx0s = (dvec3 *)(w + L.tx0s);
+    q.zs = (dvec3 *)(w + L.zs);
+    q.xf = (float4 *)(w + L.xf);
+    q.fref = (dvec3 *)(w + L.fref);
+    q.perm = (int32_t *)(w + L.perm);
+    q.tperm = (int32_t *)(w + L.tperm);
+    q.norder = (int32_t *)(w + L.norder);
+    q.rank = (int32_t *)(w + L.rank);
+    q.cellid = (int32_t *)(w + L.cellid);
+    q.nnb = (int32_t *)(w + L.nnb);
+    q.cell_count = (int32_t *)(w + L.cell_count);
+    q.cell_start = (int32_t *)(w + L.cell_start);
+    q.nl = (int32_t *)(w + L.nl);
+    q.nl_cnt = (int32_t *)(w + L.nl_cnt);
+    q.sl = (int32_t *)(w + L.sl);
+    q.mom = (void *)(w + L.mom);
+    q.e_s = (double *)(w + L.e_s);
+    q.part1 = (double *)(w + L.part1);
+    q.part2 = (double *)(w + L.part2);
+    q.disp_max = (double *)(w + L.disp_max);
+    q.work = (int32_t *)(w + L.work);
+    q.n_work = (int32_t *)(w + L.n_work);
+    q.desc = (const SysDesc *)(w + L.desc);
+    q.state = (SysState *)(w + L.state);
+    q.tiles = (const Tile *)(w + L.tiles);
+    q.groups = (const Group *)(w + L.groups);
+    q.log = (double *)(w + L.log);
+}
+
+// Fresh per-system state of a set-up: boxes from the descriptors, no strain,
+// unit integrator factors.
+void initial_states(const swfe_system_desc *d, int n_sys, SysState *st)
+{
+    for (int i = 0; i < n_sys; ++i) {
+        SysState &x = st[i];
+        memset(&x, 0, sizeof x);
+        for (int k = 0; k < 3; ++k) {
+            x.box[k] = d[i].box[k];
+            x.box_build[k] = d[i].box[k];
+            x.pscale[k] = 1.0;
+        }
+        for (int k = 0; k < 3; ++k) x.decay[k] = x.phi[k] = x.grow[k] = x.psi[k] = 1.0;
+    }
+}
+
+// Launch parameters of a batch; fx_chunk (8 * kFxChunks runs) may be NULL,
+// which runs the tiles in order.
+Ctl make_ctl_raw(const SysDesc *desc, int n_sys, int n_tiles, int n_groups, int64_t n_total, double dt,
+                 uint64_t seed, int list_cap, int in_step, int flags, int force_rebuild, int log_every,
+                 int log_cap, const int32_t *fx_chunk)
+{
+    Ctl k{};
+    k.n_total = n_total;
+    k.n_sys = n_sys;
+    k.n_tiles = n_tiles;
+    k.n_groups = n_groups;
+    k.dt = dt;
+    k.seed = seed;
+    k.flags = flags;
+    k.list_cap = list_cap;
+    k.list16 = 1;
+    k.has_uf = 0;
+    for (int i = 0; i < n_sys; ++i) {
+        k.list16 &= desc[i].n <= 65536 ? 1 : 0;
+        k.has_uf |= desc[i].mode == MODE_UF ? 1 : 0;
+    }
+    k.in_step = in_step;
+    k.force_rebuild = force_rebuild;
+    k.log_every = log_every;
+    k.log_cap = log_cap;
+    const int nc = 8 * kFxChunks;
+    k.fx_len = std::max(1, (k.n_tiles + nc - 1) / nc);
+    for (int q = 0; q < nc; ++q) k.fx_chunk[q] = fx_chunk ? fx_chunk[q] : q;
+    return k;
 }
 
 Ctl make_ctl(const swfe_ctx *c, int in_step, int flags, int force_rebuild)
 {
-    Ctl k{};
-    k.n_total = c->n_total;
-    k.n_sys = c->n_sys;
-    k.n_tiles = (int32_t)c->tiles.size();
-    k.n_groups = (int32_t)c->plan.groups.size();
-    k.dt = c->dt;
-    k.seed = c->seed;
-    k.flags = flags;
-    k.list_cap = c->plan.list_cap;
-    k.list16 = 1;
-    for (const SysDesc &d : c->plan.desc) k.list16 &= d.n <= 65536 ? 1 : 0;
-    k.has_uf = 0;
-    for (const SysDesc &d : c->plan.desc) k.has_uf |= d.mode == MODE_UF ? 1 : 0;
-    k.in_step = in_step;
-    k.force_rebuild = force_rebuild;
-    k.log_every = c->log_every;
-    k.log_cap = c->log_cap;
     const int nc = 8 * kFxChunks;
-    k.fx_len = std::max(1, (k.n_tiles + nc - 1) / nc);
-    const bool costed = (int)c->fx_chunk.size() == nc && c->fx_tiles == k.n_tiles;
-    for (int q = 0; q < nc; ++q) k.fx_chunk[q] = costed ? c->fx_chunk[q] : q;
-    return k;
+    const bool costed = (int)c->fx_chunk.size() == nc && c->fx_tiles == (int)c->tiles.size();
+    return make_ctl_raw(c->plan.desc.data(), c->n_sys, (int)c->tiles.size(), (int)c->plan.groups.size(), c->n_total,
+                        c->dt, c->seed, c->plan.list_cap, in_step, flags, force_rebuild, c->log_every, c->log_cap,
+                        costed ? c->fx_chunk.data() : nullptr);
 }
 
 // Runs of tiles dealt to the XCDs by the force passes' cost: an atom costs
@@ -414,16 +531,25 @@ int enqueue_rebuild(swfe_ctx *c, const DevPtrs &p, const Ctl &k, hipStream_t s)
 }
 
 // Caller positions -> forced list rebuild -> interaction -> caller arrays
-// (scatter_what: bits of k_scatter).
+// (scatter_what: bits of k_scatter), for launch parameters k (a forced
+// rebuild outside a step).
+hipError_t enqueue_forces_raw(const Ctl &k, const DevPtrs &p, const SwParams &sw, int mixed, int block,
+                              int scatter_what, hipStream_t s)
+{
+    hipError_t e = launch_gather(k, p, block, 0, s);
+    for (int stage = 0; stage < kRebuildStages && e == hipSuccess; ++stage)
+        e = launch_rebuild(k, p, sw, block, stage, s);
+    if (e == hipSuccess) e = launch_pass1(k, p, sw, mixed, block, s);
+    if (e == hipSuccess) e = launch_pass2(k, p, sw, mixed, block, s);
+    if (e == hipSuccess) e = launch_finalize(k, p, sw, s);
+    if (e == hipSuccess) e = launch_scatter(k, p, block, scatter_what, s);
+    return e;
+}
+
 int enqueue_forces(swfe_ctx *c, const DevPtrs &p, int flags, int scatter_what, hipStream_t s)
 {
     Ctl k = make_ctl(c, 0, flags, 1);
-    HIPCHK(c, launch_gather(k, p, c->block, 0, s));
-    RCHK(enqueue_rebuild(c, p, k, s));
-    HIPCHK(c, launch_pass1(k, p, c->sw, c->mixed, c->block, s));
-    HIPCHK(c, launch_pass2(k, p, c->sw, c->mixed, c->block, s));
-    HIPCHK(c, launch_finalize(k, p, c->sw, s));
-    HIPCHK(c, launch_scatter(k, p, c->block, scatter_what, s));
+    HIPCHK(c, enqueue_forces_raw(k, p, c->sw, c->mixed, c->block, scatter_what, s));
     return SWFE_OK;
 }
 
@@ -446,19 +572,17 @@ int read_states(swfe_ctx *c, std::vector<SysState> &st, hipStream_t s)
     return SWFE_OK;
 }
 
-// First pending device error as a status code; clears the device bits.
-int take_device_error(swfe_ctx *c, const std::vector<SysState> &st, hipStream_t s)
+// Status code and message of the first system with device error bits (c
+// may be NULL); SWFE_OK when none is set.
+int device_error_status(swfe_ctx *c, const SysState *st, int n_sys)
 {
     int bits = 0, who = -1;
-    for (int i = 0; i < c->n_sys; ++i)
+    for (int i = 0; i < n_sys; ++i)
         if (st[i].err && who < 0) {
             bits = st[i].err;
             who = i;
         }
     if (!bits) return SWFE_OK;
-    Ctl k = make_ctl(c, 0, 0, 0);
-    HIPCHK(c, launch_clear_err(k, c->ptrs, s));
-    HIPCHK(c, hipStreamSynchronize(s));
     char msg[200];
     const char *what = (bits & ERR_NONFINITE) ? "non-finite value"
                        : (bits & ERR_OVERFLOW) ? "neighbour list overflow (list or short-list capacity exceeded)"
@@ -470,6 +594,18 @@ int take_device_error(swfe_ctx *c, const std::vector<SysState> &st, hipStream_t 
                : (bits & ERR_BOX) ? SWFE_E_BOX_TOO_SMALL
                                   : SWFE_E_DCCI_SINGULAR;
     return fail(c, code, msg);
+}
+
+// First pending device error as a status code; clears the device bits.
+int take_device_error(swfe_ctx *c, const std::vector<SysState> &st, hipStream_t s)
+{
+    bool any = false;
+    for (int i = 0; i < c->n_sys; ++i) any = any || st[i].err != 0;
+    if (!any) return SWFE_OK;
+    Ctl k = make_ctl(c, 0, 0, 0);
+    HIPCHK(c, launch_clear_err(k, c->ptrs, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return device_error_status(c, st.data(), c->n_sys);
 }
 
 }  // namespace
@@ -491,7 +627,11 @@ void swfe_destroy(swfe_ctx *ctx)
     delete ctx;
 }
 
-const char *swfe_last_error(const swfe_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *swfe_last_error(const swfe_ctx *ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_free_err[0] ? g_free_err : "null context";
+}
 
 int swfe_workspace_bytes(const swfe_system_desc *d, int32_t n_sys, const swfe_sw_params *p, size_t *bytes)
 {
@@ -541,11 +681,10 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     ctx->dt = dt;
     ctx->seed = seed;
     ctx->buf = *b;
+    ctx->forces_stale = false;
     if (ctx->block != 64 && ctx->block != 128 && ctx->block != 256) ctx->block = 256;
     build_tiles(ctx);
 
-    char *w = (char *)b->workspace;
-    const Layout &L = ctx->plan.lay;
     DevPtrs &q = ctx->ptrs;
     q = DevPtrs{};
     q.x = b->x;
@@ -553,53 +692,10 @@ int swfe_init_system(swfe_ctx *ctx, const swfe_system_desc *d, int32_t n_sys, co
     q.f = b->f;
     q.x0 = b->x0;
     q.e_atom = b->e_atom;
-    q.xs = (double4 *)(w + L.xs);
-    q.vs = (dvec3 *)(w + L.vs);
-    q.fs = (dvec3 *)(w + L.fs);
-    q.x0s = (dvec3 *)(w + L.x0s);
-    q.xb = (dvec3 *)(w + L.xb);
-    q.txs = (double4 *)(w + L.txs);
-    q.tvs = (dvec3 *)(w + L.tvs);
-    q.tfs = (dvec3 *)(w + L.tfs);
-    q.tx0s = (dvec3 *)(w + L.tx0s);
-    q.zs = (dvec3 *)(w + L.zs);
-    q.xf = (float4 *)(w + L.xf);
-    q.fref = (dvec3 *)(w + L.fref);
-    q.perm = (int32_t *)(w + L.perm);
-    q.tperm = (int32_t *)(w + L.tperm);
-    q.norder = (int32_t *)(w + L.norder);
-    q.rank = (int32_t *)(w + L.rank);
-    q.cellid = (int32_t *)(w + L.cellid);
-    q.nnb = (int32_t *)(w + L.nnb);
-    q.cell_count = (int32_t *)(w + L.cell_count);
-    q.cell_start = (int32_t *)(w + L.cell_start);
-    q.nl = (int32_t *)(w + L.nl);
-    q.nl_cnt = (int32_t *)(w + L.nl_cnt);
-    q.sl = (int32_t *)(w + L.sl);
-    q.mom = (void *)(w + L.mom);
-    q.e_s = (double *)(w + L.e_s);
-    q.part1 = (double *)(w + L.part1);
-    q.part2 = (double *)(w + L.part2);
-    q.disp_max = (double *)(w + L.disp_max);
-    q.work = (int32_t *)(w + L.work);
-    q.n_work = (int32_t *)(w + L.n_work);
-    q.desc = (const SysDesc *)(w + L.desc);
-    q.state = (SysState *)(w + L.state);
-    q.tiles = (const Tile *)(w + L.tiles);
-    q.groups = (const Group *)(w + L.groups);
-    q.log = (double *)(w + L.log);
+    carve(q, (char *)b->workspace, ctx->plan.lay);
 
     std::vector<SysState> st(n_sys);
-    for (int i = 0; i < n_sys; ++i) {
-        SysState &x = st[i];
-        memset(&x, 0, sizeof x);
-        for (int k = 0; k < 3; ++k) {
-            x.box[k] = d[i].box[k];
-            x.box_build[k] = d[i].box[k];
-            x.pscale[k] = 1.0;
-        }
-        for (int k = 0; k < 3; ++k) x.decay[k] = x.phi[k] = x.grow[k] = x.psi[k] = 1.0;
-    }
+    initial_states(d, n_sys, st.data());
     HIPCHK(ctx, hipMemcpyAsync(q.state, st.data(), sizeof(SysState) * n_sys, hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipMemsetAsync(q.cell_count, 0, 4 * (size_t)ctx->plan.cells, s));
     HIPCHK(ctx, hipMemsetAsync(q.disp_max, 0, 8 * 2 * (size_t)n_sys, s));
@@ -660,8 +756,22 @@ int swfe_compute_forces(swfe_ctx *ctx, uint32_t flags, const double *strain, con
     }
     RCHK(enqueue_forces(ctx, p, (int)flags, 2 | 4 | 8, s));
     if (flags & SWFE_STRAIN) HIPCHK(ctx, launch_set_pscale(k, p, nullptr, s));
+    ctx->forces_stale = (flags & SWFE_STRAIN) != 0;
     return SWFE_OK;
 }
+
+namespace {
+// Dynamics start from forces, energies and virial of the unstrained
+// positions: after a strained evaluation the interaction is evaluated again
+// (f of the caller is overwritten with the unstrained forces).
+int refresh_forces(swfe_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->forces_stale) return SWFE_OK;
+    RCHK(enqueue_forces(ctx, ctx->ptrs, 0, 2, s));
+    ctx->forces_stale = false;
+    return SWFE_OK;
+}
+}  // namespace
 
 int swfe_set_params(swfe_ctx *ctx, const swfe_sw_params *p)
 {
@@ -705,6 +815,7 @@ int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *
     if (n_steps < 0) return fail(ctx, SWFE_E_INVALID_ARG, "n_steps < 0");
     if (n_steps == 0) return SWFE_OK;
     hipStream_t s = (hipStream_t)stream;
+    RCHK(refresh_forces(ctx, s));
     Ctl k = make_ctl(ctx, 1, 0, 0);
     HIPCHK(ctx, launch_gather(k, ctx->ptrs, ctx->block, 1, s));
     HIPCHK(ctx, launch_begin_step(k, ctx->ptrs, ctx->sw, n_steps, s));
@@ -901,6 +1012,7 @@ int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     if (!ms || n_steps <= 0) return fail(ctx, SWFE_E_INVALID_ARG, "ms output and n_steps > 0 required");
     hipStream_t s = (hipStream_t)stream;
+    RCHK(refresh_forces(ctx, s));
     const int nk = SWFE_NUM_KERNELS;
     std::vector<hipEvent_t> ev((size_t)(nk + 1) * n_steps);
     for (auto &e : ev) HIPCHK(ctx, hipEventCreate(&e));

@@ -30,7 +30,25 @@ enum : int {
 };
 
 // Device error bits (per system, sticky until read by the host).
-enum : int { ERR_OVERFLOW = 1, ERR_NONFINITE = 2, ERR_DCCI = 4, ERR_BOX = 8 };
+enum : int { ERR_OVERFLOW = 1, ERR_NONFINITE = 2, ERR_DCCI = 4, ERR_BOX = 8, ERR_PERSIST = 16 };
+
+// Persistent step kernel: the systems of the batch are dealt to the 8 XCDs
+// (whole reduction groups), and the workgroups running on an XCD step that
+// XCD's systems, meeting at barriers of their own XCD.
+constexpr int kXcds = 8;
+constexpr int kPersistMaxSysPerXcd = 256;  // systems one XCD may own
+constexpr int kSyncWords = 16 * 16;        // 64-bit words of the barrier area
+// barrier-area word offsets (each counter on its own 128-byte line)
+constexpr int SYNC_START = 0;              // arrivals at the start-up barrier
+constexpr int SYNC_XCD = 16;               // 16 * (1 + x): barrier counter of XCD x
+constexpr int SYNC_REG = 16 * 9;           // + x: workgroups that registered on XCD x
+constexpr int SYNC_ABORT = 16 * 10;        // non-zero: a wait gave up; every block leaves
+
+struct XcdPlan {
+    int32_t tile_off[kXcds + 1];   // XCD x steps tiles xtiles[tile_off[x] .. tile_off[x + 1])
+    int32_t group_off[kXcds + 1];  // and groups xgroups[group_off[x] .. group_off[x + 1])
+    int32_t sys_off[kXcds + 1];    // whose systems are xsys[sys_off[x] .. sys_off[x + 1])
+};
 
 enum : int {
     MODE_FORCE = 0, MODE_NVE = 1, MODE_NVT = 2, MODE_FL = 3,
@@ -154,6 +172,10 @@ struct DevPtrs {
     const Tile *tiles;
     const Group *groups;
     double *log;
+    // persistent step kernel: per-XCD tile, group and system lists, each
+    // system's index in its XCD's list, and the barrier area
+    int32_t *xtiles, *xtloc, *xgroups, *xsys;  // xtloc: XCD-list index of each listed tile's system
+    unsigned long long *sync;
     // per-call outputs of compute_forces
     const double *grad_scale;
     double *grad_x;
@@ -179,5 +201,12 @@ hipError_t launch_begin_step(const Ctl &c, const DevPtrs &p, const SwParams &sw,
 hipError_t launch_reset_schedule(const Ctl &c, const DevPtrs &p, hipStream_t s);
 hipError_t launch_set_pscale(const Ctl &c, const DevPtrs &p, const double *diag, hipStream_t s);
 hipError_t launch_clear_err(const Ctl &c, const DevPtrs &p, hipStream_t s);
+hipError_t launch_zero_words(void *w, size_t bytes, hipStream_t s);
+// Persistent step kernel (cooperative launch of `grid` blocks of `block`
+// threads) running n_steps steps, then the check that turns a failed wait
+// into ERR_PERSIST on every system.
+int persist_blocks_per_cu(int mixed, int block);
+hipError_t launch_persist(const Ctl &c, const DevPtrs &p, const SwParams &sw, const XcdPlan &xp, int mixed,
+                          int block, int grid, int64_t n_steps, hipStream_t s);
 
 }  // namespace swfe

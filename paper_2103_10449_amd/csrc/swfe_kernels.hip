@@ -43,6 +43,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace swfe {
 
 // ------------------------------------------------------------------ utils --
@@ -98,12 +100,15 @@ __device__ __forceinline__ double list_radius(const SwParams &sw, const SysDesc 
 }
 
 // Cell grid for the list build: cells of at least the list radius, capped.
+// The range tests run in FP64 before any conversion to int, so a
+// non-finite box or position (which the step flags as an error) still
+// yields an index inside the grid: converting NaN or an out-of-range double
+// to int would be undefined.
 __device__ __forceinline__ void cell_grid(const SysDesc &d, const double box[3], double rl, int nc[3])
 {
     for (int k = 0; k < 3; ++k) {
-        int n = (int)floor(box[k] / rl);
-        n = n < 1 ? 1 : n;
-        nc[k] = n > d.nc_max[k] ? d.nc_max[k] : n;
+        const double n = floor(box[k] / rl);
+        nc[k] = n >= 1.0 ? (n < (double)d.nc_max[k] ? (int)n : d.nc_max[k]) : 1;
     }
 }
 
@@ -111,9 +116,8 @@ __device__ __forceinline__ int cell_coord(double x, double ibox, int nc)
 {
     double s = x * ibox;
     s -= floor(s);
-    int c = (int)(s * nc);
-    c = c < 0 ? 0 : c;
-    return c >= nc ? nc - 1 : c;
+    const double f = s * nc;
+    return f >= 0.0 ? (f < (double)nc ? (int)f : nc - 1) : 0;
 }
 
 __device__ __forceinline__ int cell_of_pos(const double4 &x, const double ibox[3], const int nc[3])
@@ -219,6 +223,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double *out)
         for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
         out[threadIdx.x] = s;
     }
+    __syncthreads();  // red may be written again by the block's next call
 }
 
 __device__ __forceinline__ double block_max(double v)
@@ -231,6 +236,7 @@ __device__ __forceinline__ double block_max(double v)
     __syncthreads();
     double m = 0.0;
     for (int w = 0; w < nw; ++w) m = fmax(m, red[w]);
+    __syncthreads();  // red may be written again by the block's next call
     return m;
 }
 
@@ -262,7 +268,8 @@ __global__ void __launch_bounds__(256) k_gather(Ctl c, DevPtrs p, int with_f)
     eff_box(st, box, ibox);
     p.xs[t] = x;
     p.xf[t] = pos_f32(x, box, ibox);
-    p.vs[t] = make_dvec3(p.v[i], p.v[N + i], p.v[2 * N + i]);
+    // force evaluations without dynamics may pass no velocities
+    p.vs[t] = p.v ? make_dvec3(p.v[i], p.v[N + i], p.v[2 * N + i]) : make_dvec3(0.0, 0.0, 0.0);
     if (with_f) p.fs[t] = make_dvec3(p.f[i], p.f[N + i], p.f[2 * N + i]);
     if (p.x0) p.x0s[t] = make_dvec3(p.x0[i], p.x0[N + i], p.x0[2 * N + i]);
 }
@@ -338,10 +345,8 @@ __global__ void __launch_bounds__(256) k_fill_noise(Ctl c, DevPtrs p)
 // A half drift with isotropic box scaling, O Langevin step with zero-sum
 // noise, A half drift.  Then the displacement from the list-build position
 // (scaled with the box) for the rebuild test.
-__global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw)
+__device__ __forceinline__ void integrate_tile(const Ctl &c, const DevPtrs &p, const SwParams &sw, int ti)
 {
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
     const Tile tile = p.tiles[ti];
     const int sys = tile.sys;
     const SysDesc &d = p.desc[sys];
@@ -396,6 +401,12 @@ __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw
                   (unsigned long long)__double_as_longlong(dmax));
 }
 
+__global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw)
+{
+    const int ti = tile_of_block(c);
+    if (ti >= 0) integrate_tile(c, p, sw, ti);
+}
+
 // --------------------------------------------------------------- rebuild ---
 // Does this system's Verlet list need a rebuild?  A pair now within rc that
 // is missing from the list was at least rc + skin apart at the build; after
@@ -417,25 +428,33 @@ __device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, i
 // Binning of the atoms of every system whose list is stale (each block
 // takes the decision for its tile's system; the scan stage takes the same
 // decision from the same inputs).  The rebuild work list starts empty.
+__device__ __forceinline__ void rb_count_tile(const DevPtrs &p, const SwParams &sw, int ti)
+{
+    const Tile tile = p.tiles[ti];
+    for (int a = threadIdx.x; a < tile.count; a += blockDim.x) {
+        const int t = tile.start + a;
+        bin_atom(p, sw, p.desc[tile.sys], p.state[tile.sys], t, p.xs[t]);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_rb_count(Ctl c, DevPtrs p, SwParams sw)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) p.n_work[0] = 0;
     const int ti = tile_of_block(c);
     if (ti < 0) return;
-    const Tile tile = p.tiles[ti];
-    if (!list_stale(c, p, sw, tile.sys)) return;
-    if ((int)threadIdx.x >= tile.count) return;
-    const int t = tile.start + threadIdx.x;
-    bin_atom(p, sw, p.desc[tile.sys], p.state[tile.sys], t, p.xs[t]);
+    if (!list_stale(c, p, sw, p.tiles[ti].sys)) return;
+    rb_count_tile(p, sw, ti);
 }
 
-// One workgroup per system: the rebuild decision; for a stale list the
-// exclusive scan of the cell counts into cell starts (sorted positions),
-// the counts cleared for the next binning, and the system's tiles appended
-// to the work list of the later stages.
-__global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwParams sw)
+// For one system, by all threads of a block: clear the next step's
+// displacement slot, and for a stale list (rb) the exclusive scan of the cell
+// counts into cell starts (sorted positions), the counts cleared for the
+// next binning, the build box and the rebuild count; with `append` the
+// system's tiles go to the work list of the later stages.
+// NT bounds the block's thread count (the LDS of the scan).
+template <int NT>
+__device__ void rb_scan_sys(const Ctl &c, const DevPtrs &p, const SwParams &sw, int sys, bool rb, bool append)
 {
-    const int sys = blockIdx.x;
     SysState &st = p.state[sys];
     const SysDesc &d = p.desc[sys];
     double box[3], ibox[3];
@@ -444,59 +463,68 @@ __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwPa
     cell_grid(d, box, list_radius(sw, d), nc3);
     const int nc = nc3[0] * nc3[1] * nc3[2];
     int32_t *cnt = p.cell_count + d.cell_base;
-    const int tid = threadIdx.x;
-    __shared__ int rb_s, at_s;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    __shared__ int at_s;
     if (tid == 0) {
-        const bool rb = list_stale(c, p, sw, sys);
         // clear the slot the next step's integrate fills (both on a forced build)
         p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
         if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
-        rb_s = rb ? 1 : 0;
-        at_s = rb ? atomicAdd(&p.n_work[0], d.tile_end - d.tile_begin) : 0;
+        at_s = rb && append ? atomicAdd(&p.n_work[0], d.tile_end - d.tile_begin) : 0;
     }
     __syncthreads();
-    if (!rb_s) return;
-    for (int q = tid; q < d.tile_end - d.tile_begin; q += kSortThreads) p.work[at_s + q] = d.tile_begin + q;
-    int32_t *start = p.cell_start + d.cell_base + sys;  // nc + 1 entries
-    const int off = (int)d.off, n = (int)d.n;
+    if (rb) {
+        if (append)
+            for (int q = tid; q < d.tile_end - d.tile_begin; q += nth) p.work[at_s + q] = d.tile_begin + q;
+        int32_t *start = p.cell_start + d.cell_base + sys;  // nc + 1 entries
+        const int off = (int)d.off, n = (int)d.n;
+        __shared__ int32_t part[NT];
+        const int per = (nc + nth - 1) / nth;
+        const int lo = min(tid * per, nc), hi = min(lo + per, nc);
+        int sum = 0;
+        for (int q = lo; q < hi; ++q) sum += cnt[q];
+        part[tid] = sum;
+        __syncthreads();
+        for (int o = 1; o < nth; o <<= 1) {
+            const int add = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        int run = off + part[tid] - sum;
+        for (int q = lo; q < hi; ++q) {
+            start[q] = run;
+            run += cnt[q];
+            cnt[q] = 0;
+        }
+        if (tid == 0) {
+            start[nc] = off + n;
+            for (int k = 0; k < 3; ++k) st.box_build[k] = box[k];
+            st.n_rebuild += 1;
+        }
+    }
+    __syncthreads();  // at_s and part may be written again by the block's next call
+}
 
-    __shared__ int32_t part[kSortThreads];
-    const int per = (nc + kSortThreads - 1) / kSortThreads;
-    const int lo = min(tid * per, nc), hi = min(lo + per, nc);
-    int sum = 0;
-    for (int q = lo; q < hi; ++q) sum += cnt[q];
-    part[tid] = sum;
+// One workgroup per system: the rebuild decision, then the scan above with
+// the stale systems' tiles appended to the work list of the later stages.
+__global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwParams sw)
+{
+    const int sys = blockIdx.x;
+    __shared__ int rb_s;
+    if (threadIdx.x == 0) rb_s = list_stale(c, p, sw, sys) ? 1 : 0;
     __syncthreads();
-    for (int o = 1; o < kSortThreads; o <<= 1) {
-        const int add = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += add;
-        __syncthreads();
-    }
-    int run = off + part[tid] - sum;
-    for (int q = lo; q < hi; ++q) {
-        start[q] = run;
-        run += cnt[q];
-        cnt[q] = 0;
-    }
-    if (tid == 0) {
-        start[nc] = off + n;
-        for (int k = 0; k < 3; ++k) st.box_build[k] = box[k];
-        st.n_rebuild += 1;
-    }
+    rb_scan_sys<kSortThreads>(c, p, sw, sys, rb_s != 0, true);
 }
 
 // Atom data into its cell's segment of the staging arrays (slot by rank, so
 // the order inside a cell is not yet fixed).
-__global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p)
+__device__ __forceinline__ void rb_scatter_tile(const DevPtrs &p, int ti)
 {
-    const int n_work = p.n_work[0];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const Tile tile = p.tiles[p.work[w]];
-        if ((int)threadIdx.x >= tile.count) continue;
+    const Tile tile = p.tiles[ti];
+    for (int a = threadIdx.x; a < tile.count; a += blockDim.x) {
         const int sys = tile.sys;
         const SysDesc &d = p.desc[sys];
-        const int t = tile.start + threadIdx.x;
+        const int t = tile.start + a;
         const int cell = p.cellid[t];
         const int s = p.cell_start[d.cell_base + sys + cell] + p.rank[t];
         p.txs[s] = p.xs[t];
@@ -508,17 +536,21 @@ __global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p)
     }
 }
 
-// Final order: inside a cell atoms follow the caller's atom index.  Each
-// staged atom counts the smaller indices of its cell and moves there.
-__global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
+__global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p)
 {
     const int n_work = p.n_work[0];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const Tile tile = p.tiles[p.work[w]];
-        if ((int)threadIdx.x >= tile.count) continue;
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) rb_scatter_tile(p, p.work[w]);
+}
+
+// Final order: inside a cell atoms follow the caller's atom index.  Each
+// staged atom counts the smaller indices of its cell and moves there.
+__device__ __forceinline__ void rb_order_tile(const DevPtrs &p, int ti)
+{
+    const Tile tile = p.tiles[ti];
+    for (int a = threadIdx.x; a < tile.count; a += blockDim.x) {
         const int sys = tile.sys;
         const SysDesc &d = p.desc[sys];
-        const int i = tile.start + threadIdx.x;
+        const int i = tile.start + a;
         const int cell = p.norder[i];
         const int32_t *start = p.cell_start + d.cell_base + sys;
         const int b = start[cell], e = start[cell + 1];
@@ -537,6 +569,12 @@ __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
         if (p.x0) p.x0s[s] = p.tx0s[i];
         p.perm[s] = key;
     }
+}
+
+__global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
+{
+    const int n_work = p.n_work[0];
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) rb_order_tile(p, p.work[w]);
 }
 
 // Verlet-list storage.  With 32-bit entries, entry k of sorted atom s is the
@@ -616,13 +654,13 @@ __device__ __forceinline__ void list_batch(const Ctl &c, const int32_t *nl, int 
 // that no cell is visited twice).  32 lanes per atom, one per stencil cell:
 // each lane marks the candidates of its cell, a prefix sum over the lanes
 // gives every cell its slot range, so the list is in stencil-cell order and,
-// inside a cell, in sorted order.  Blocks of 256 threads hold 8 atoms; S
-// blocks cover one tile.
+// inside a cell, in sorted order.  A block holds blockDim / 32 atoms; sub
+// numbers the blocks' shares of one tile.
 __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const SwParams &sw, int ti, int sub)
 {
     const Tile tile = p.tiles[ti];
     const int sys = tile.sys;
-    const int a_loc = sub * 8 + (threadIdx.x >> 5);
+    const int a_loc = sub * (int)(blockDim.x >> 5) + (threadIdx.x >> 5);
     const int lane = threadIdx.x & 31;
     const bool valid = a_loc < tile.count;
     const SysDesc &d = p.desc[sys];
@@ -761,17 +799,15 @@ struct Batch {
     static constexpr int P2 = sizeof(R) == 4 ? 4 : 2;
 };
 
+// lsl: [kLdsShort][blockDim.x] short-list entries in LDS
 template <typename R, bool GRAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
+__device__ __forceinline__ void pass1_tile(const Ctl &c, const DevPtrs &p, const SwParams &sw, int ti, int32_t *lsl)
 {
-    extern __shared__ int32_t lsl[];  // [kLdsShort][blockDim.x] short-list entries
     const int lb = blockDim.x, lt = threadIdx.x;
     constexpr int NV = 20;  // E2, virial 9, dtheta 9, E3
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
     const Tile tile = p.tiles[ti];
     const int sys = tile.sys;
     const SysState &st = p.state[sys];
@@ -951,6 +987,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     block_reduce<NV>(acc, p.part1 + (int64_t)ti * kNumPart);
 }
 
+template <typename R, bool GRAD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass1(Ctl c, DevPtrs p, SwParams sw)
+{
+    extern __shared__ int32_t lsl[];
+    const int ti = tile_of_block(c);
+    if (ti >= 0) pass1_tile<R, GRAD>(c, p, sw, ti, lsl);
+}
+
 // ------------------------------------------------------ UF reference ---
 // Uhlenbeck-Ford reference of the UF systems (section 4.1; model of Leite et
 // al.): phi(r) = -p kB T ln(1 - exp(-(r/sigma)^2)) over each atom's whole
@@ -958,10 +1002,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 // the tile's energy into its pass-1 row.  Launched only when a UF system is
 // present; other tiles leave at once.
 template <typename R>
-__global__ void __launch_bounds__(256) k_uf(Ctl c, DevPtrs p)
+__device__ __forceinline__ void uf_tile(const Ctl &c, const DevPtrs &p, int ti)
 {
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
     const Tile tile = p.tiles[ti];
     const SysDesc &d = p.desc[tile.sys];
     if (d.mode != MODE_UF) return;
@@ -1005,6 +1047,13 @@ __global__ void __launch_bounds__(256) k_uf(Ctl c, DevPtrs p)
     }
     double acc[1] = {e};
     block_reduce<1>(acc, p.part1 + (int64_t)ti * kNumPart + P_UUF);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_uf(Ctl c, DevPtrs p)
+{
+    const int ti = tile_of_block(c);
+    if (ti >= 0) uf_tile<R>(c, p, ti);
 }
 
 // ---------------------------------------------------------------- pass 2 ---
@@ -1292,6 +1341,7 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
     }
     __syncthreads();
     for (int q = 0; q < nq; ++q) block_copy(&p.state[sid[q]], &sst[q], sizeof(SysState));
+    __syncthreads();  // the LDS copies may be written again by the block's next group
 }
 
 // Normals of atom t's next O step: stored in zs and added to the tile's
@@ -1309,14 +1359,12 @@ __device__ __forceinline__ void next_normals(const Ctl &c, const SysDesc &d, con
 }
 
 template <typename R, bool GRAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass2(Ctl c, DevPtrs p, SwParams sw)
+__device__ __forceinline__ void pass2_tile(const Ctl &c, const DevPtrs &p, const SwParams &sw, int ti)
 {
     constexpr int NV = kNumPart;  // -, virial 9, dtheta 9, U_ref, K per axis 3, noise 3
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    const int ti = tile_of_block(c);
-    if (ti < 0) return;
     const Tile tile = p.tiles[ti];
     const int sys = tile.sys;
     const SysDesc &d = p.desc[sys];
@@ -1442,6 +1490,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     block_reduce<NV>(acc, p.part2 + (int64_t)ti * kNumPart);
 }
 
+template <typename R, bool GRAD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) k_pass2(Ctl c, DevPtrs p, SwParams sw)
+{
+    const int ti = tile_of_block(c);
+    if (ti >= 0) pass2_tile<R, GRAD>(c, p, sw, ti);
+}
+
 // One block per group: fixed-order reductions of the group's tiles and the
 // scalar update (barostat, switch and work, dCCI coupling, next factors).
 __global__ void __launch_bounds__(256) k_finalize(Ctl c, DevPtrs p, SwParams sw)
@@ -1492,10 +1547,218 @@ __global__ void k_set_pscale(Ctl c, DevPtrs p, const double *diag)
     for (int k = 0; k < 3; ++k) p.state[s].pscale[k] = diag ? 1.0 + diag[3 * s + k] : 1.0;
 }
 
+// Zero n 32-bit words (a kernel rather than a memset, so that a caller may
+// capture the call).
+__global__ void k_zero_words(uint32_t *w, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0u;
+}
+
 __global__ void k_clear_err(Ctl c, DevPtrs p)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < c.n_sys) p.state[s].err = 0;
+}
+
+// ------------------------------------------------------- persistent step ---
+// One cooperative launch runs n_steps whole steps.  The systems are dealt to
+// the XCDs beforehand (whole reduction groups, by cost); each workgroup reads
+// the XCD it runs on from the hardware and steps only that XCD's systems,
+// meeting the XCD's other workgroups at barriers between the stages of a
+// step.  During the kernel a system's data is written and read only by
+// workgroups of its own XCD, whose L2 they share: a barrier needs the
+// arrivals' stores complete in that L2 (the L1 writes through) and each
+// arriving CU's L1 invalidated, but no L2 write-back.  Every wait is bounded:
+// a wait that gives up raises the abort word, every workgroup then leaves,
+// and the check kernel that follows marks every system with ERR_PERSIST.
+constexpr long kSpinLimit = 1L << 22;  // polls of one wait (seconds) before giving up
+
+__device__ __forceinline__ unsigned long long ld_agent(unsigned long long *w)
+{
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_agent(unsigned long long *w, unsigned long long v)
+{
+    __hip_atomic_fetch_add(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: wait until *w >= target; false when the kernel is abandoned.
+__device__ bool wait_at_least(unsigned long long *w, unsigned long long target, unsigned long long *abort_w)
+{
+    long spins = 0;
+    while (ld_agent(w) < target) {
+        if (ld_agent(abort_w)) return false;
+        if (++spins > kSpinLimit) {
+            __hip_atomic_store(abort_w, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Barrier of the nb workgroups of one XCD (counter ctr, reaching target).
+__device__ bool xcd_barrier(unsigned long long *ctr, unsigned long long target, unsigned long long *abort_w,
+                            int nb, int *flag_s)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        if (nb > 1) {
+            add_agent(ctr, 1ull);
+            ok = wait_at_least(ctr, target, abort_w);
+        }
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        *flag_s = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return *flag_s != 0;
+}
+
+// In-place exclusive prefix of a[0 .. n) in LDS by all threads of a block
+// (at most 256); a[n] receives the total.
+__device__ void block_exclusive_scan(int32_t *a, int n)
+{
+    __shared__ int32_t part[256];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int per = (n + nth - 1) / nth;
+    const int lo = min(tid * per, n), hi = min(lo + per, n);
+    int sum = 0;
+    for (int q = lo; q < hi; ++q) sum += a[q];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < nth; o <<= 1) {
+        const int add = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+    }
+    int run = part[tid] - sum;
+    for (int q = lo; q < hi; ++q) {
+        const int v = a[q];
+        a[q] = run;
+        run += v;
+    }
+    if (tid == nth - 1) a[n] = part[nth - 1];
+    __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+k_persist(Ctl c, DevPtrs p, SwParams sw, XcdPlan xp, int64_t n_steps)
+{
+    extern __shared__ int32_t lsl[];  // pass 1's short list; the list stage's tile tables
+    __shared__ int s_flag, s_x, s_j, s_nb, s_any;
+    __shared__ unsigned char s_stale[kPersistMaxSysPerXcd];
+    unsigned long long *sync = p.sync;
+    unsigned long long *abort_w = sync + SYNC_ABORT;
+    // start-up: each workgroup joins the XCD it runs on
+    if (threadIdx.x == 0) {
+        unsigned v;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+        const int x = (int)(v & 0xFu);
+        int ok = x < kXcds ? 1 : 0;
+        int j = 0;
+        if (ok) j = (int)__hip_atomic_fetch_add(sync + SYNC_REG + x, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else __hip_atomic_store(abort_w, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        add_agent(sync + SYNC_START, 1ull);
+        if (!wait_at_least(sync + SYNC_START, gridDim.x, abort_w) || ld_agent(abort_w)) ok = 0;
+        // every XCD that owns systems needs workgroups
+        for (int y = 0; y < kXcds && ok; ++y)
+            if (xp.tile_off[y + 1] > xp.tile_off[y] && ld_agent(sync + SYNC_REG + y) == 0) ok = 0;
+        if (!ok) __hip_atomic_store(abort_w, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_x = ok ? x : 0;
+        s_j = j;
+        s_nb = ok ? (int)ld_agent(sync + SYNC_REG + x) : 0;
+        s_flag = ok;
+    }
+    __syncthreads();
+    if (!s_flag) return;
+    const int x = s_x, j = s_j, nb = s_nb;
+    const int tb = xp.tile_off[x], te = xp.tile_off[x + 1];
+    if (tb == te) return;  // this XCD owns no systems
+    const int gb = xp.group_off[x], ge = xp.group_off[x + 1];
+    const int sb = xp.sys_off[x], se = xp.sys_off[x + 1];
+    unsigned long long *ctr = sync + SYNC_XCD + 16 * x;
+    unsigned long long epoch = 0;
+    const int apb = (int)(blockDim.x >> 5);  // atoms per list-build share
+    int32_t *lpref = lsl;  // the list stage's share table (at most kLdsShort * blockDim - 1 tiles)
+#define SWFE_XCD_SYNC()                                                          \
+    if (!xcd_barrier(ctr, ++epoch * (unsigned long long)nb, abort_w, nb, &s_flag)) \
+        break
+    for (int64_t step = 0; step < n_steps; ++step) {
+        for (int i = tb + j; i < te; i += nb) integrate_tile(c, p, sw, p.xtiles[i]);
+        SWFE_XCD_SYNC();
+        // rebuild decisions of the XCD's systems, taken by every block from
+        // the same state (nothing they read changes before the count stage)
+        if (threadIdx.x == 0) s_any = 0;
+        __syncthreads();
+        for (int q = sb + (int)threadIdx.x; q < se; q += blockDim.x) {
+            const bool rb = list_stale(c, p, sw, p.xsys[q]);
+            s_stale[q - sb] = rb ? 1 : 0;
+            if (rb) s_any = 1;
+        }
+        // the displacement slot the next step's integrate fills starts at zero
+        if (threadIdx.x == 0)
+            for (int q = sb + j; q < se; q += nb) {
+                const int sys = p.xsys[q];
+                p.disp_max[2 * sys + ((p.state[sys].step + 1) & 1)] = 0.0;
+            }
+        __syncthreads();
+        if (s_any) {
+            for (int i = tb + j; i < te; i += nb)
+                if (s_stale[p.xtloc[i]]) rb_count_tile(p, sw, p.xtiles[i]);
+            SWFE_XCD_SYNC();
+            for (int q = sb + j; q < se; q += nb)
+                if (s_stale[q - sb]) rb_scan_sys<256>(c, p, sw, p.xsys[q], true, false);
+            SWFE_XCD_SYNC();
+            for (int i = tb + j; i < te; i += nb)
+                if (s_stale[p.xtloc[i]]) rb_scatter_tile(p, p.xtiles[i]);
+            SWFE_XCD_SYNC();
+            for (int i = tb + j; i < te; i += nb)
+                if (s_stale[p.xtloc[i]]) rb_order_tile(p, p.xtiles[i]);
+            SWFE_XCD_SYNC();
+            // list-build shares of the XCD's tiles (none for a tile whose
+            // list stays), and their exclusive prefix, in LDS
+            const int nt = te - tb;
+            for (int i = threadIdx.x; i < nt; i += blockDim.x)
+                lpref[i] = s_stale[p.xtloc[tb + i]] ? (p.tiles[p.xtiles[tb + i]].count + apb - 1) / apb : 0;
+            __syncthreads();
+            block_exclusive_scan(lpref, nt);
+            const int nv = lpref[nt];
+            for (int v = j; v < nv; v += nb) {
+                int lo = 0, hi = nt - 1;  // the last tile whose shares start at or before v
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (lpref[mid] <= v) lo = mid;
+                    else hi = mid - 1;
+                }
+                list_block(c, p, sw, p.xtiles[tb + lo], v - lpref[lo]);
+            }
+            SWFE_XCD_SYNC();
+        }
+        for (int i = tb + j; i < te; i += nb) {
+            const int ti = p.xtiles[i];
+            pass1_tile<R, false>(c, p, sw, ti, lsl);
+            if (c.has_uf) uf_tile<R>(c, p, ti);
+        }
+        SWFE_XCD_SYNC();
+        for (int i = tb + j; i < te; i += nb) pass2_tile<R, false>(c, p, sw, p.xtiles[i]);
+        SWFE_XCD_SYNC();
+        for (int g = gb + j; g < ge; g += nb) group_finalize(c, p, sw, p.groups[p.xgroups[g]]);
+        SWFE_XCD_SYNC();
+    }
+#undef SWFE_XCD_SYNC
+}
+
+// After a persistent launch: a wait that gave up marks every system.
+__global__ void k_persist_check(Ctl c, DevPtrs p)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < c.n_sys && p.sync[SYNC_ABORT]) p.state[s].err |= ERR_PERSIST;
 }
 
 // ----------------------------------------------------------- launchers -----
@@ -1605,9 +1868,48 @@ hipError_t launch_set_pscale(const Ctl &c, const DevPtrs &p, const double *diag,
     return hipGetLastError();
 }
 
+hipError_t launch_zero_words(void *w, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)w, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_clear_err(const Ctl &c, const DevPtrs &p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_err, dim3((c.n_sys + 63) / 64), dim3(64), 0, s, c, p);
+    return hipGetLastError();
+}
+}  // namespace swfe
+
+namespace swfe {
+int persist_blocks_per_cu(int mixed, int block)
+{
+    int n = 0;
+    const size_t lds = sizeof(int32_t) * kLdsShort * (size_t)block;
+    hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist<float>, block, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist<double>, block, lds);
+    return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_persist(const Ctl &c, const DevPtrs &p, const SwParams &sw, const XcdPlan &xp, int mixed,
+                          int block, int grid, int64_t n_steps, hipStream_t s)
+{
+    const size_t lds = sizeof(int32_t) * kLdsShort * (size_t)block;
+    Ctl cc = c;
+    DevPtrs pp = p;
+    SwParams ss = sw;
+    XcdPlan xx = xp;
+    int64_t ns = n_steps;
+    void *args[] = {&cc, &pp, &ss, &xx, &ns};
+    hipError_t e = mixed ? hipLaunchCooperativeKernel((const void *)k_persist<float>, dim3(grid), dim3(block), args,
+                                                      lds, s)
+                         : hipLaunchCooperativeKernel((const void *)k_persist<double>, dim3(grid), dim3(block), args,
+                                                      lds, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_persist_check, dim3((c.n_sys + 63) / 64), dim3(64), 0, s, c, p);
     return hipGetLastError();
 }
 }  // namespace swfe

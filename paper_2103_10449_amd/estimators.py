@@ -23,6 +23,14 @@ def dissipated_heat(w_forward, w_backward) -> float:
     return 0.5 * (float(np.mean(w_forward)) + float(np.mean(w_backward)))
 
 
+def _with_start(x0: float, x_log: np.ndarray, w_log: np.ndarray):
+    """The logged path (x, W) with its start (x0, W = 0) in front, unless the
+    log already begins there."""
+    if len(x_log) and x_log[0] == x0:
+        return x_log, w_log
+    return np.r_[x0, x_log], np.r_[0.0, w_log]
+
+
 def _work_along(x_log: np.ndarray, w_log: np.ndarray, grid: np.ndarray) -> np.ndarray:
     """Accumulated work at the grid values of the switched variable, from a
     monotone logged path (x, W)."""
@@ -31,38 +39,49 @@ def _work_along(x_log: np.ndarray, w_log: np.ndarray, grid: np.ndarray) -> np.nd
     return np.interp(grid, x_log[order], w_log[order])
 
 
-def gibbs_rs(G0: float, n_atoms: int, T0: float, lam_fwd, w_fwd, lam_bwd, w_bwd, lam_grid) -> Tuple[np.ndarray, np.ndarray]:
+def gibbs_rs(G0: float, n_atoms: int, T0: float, lam_fwd, w_fwd, lam_bwd, w_bwd, lam_grid,
+             lam_f=None) -> Tuple[np.ndarray, np.ndarray]:
     """Gibbs free energy G(P, T0/lambda) on lam_grid from reversible scaling
     (eq. Gibbs_RS): G0/lambda + (3/2) N kB T0 ln(lambda)/lambda +
     [W(1->lambda) - W(lambda->1)] / (2 lambda).
 
     lam_fwd, w_fwd: the logged lambda and accumulated work of a run from 1
-    to lambda_f (W = 0 at lambda = 1); lam_bwd, w_bwd: those of the run back
-    from lambda_f to 1.  W(lambda->1) is the backward total minus the
-    backward work done before reaching lambda.  Returns (T, G)."""
+    to lambda_f; lam_bwd, w_bwd: those of the run back from lambda_f to 1.
+    Each run starts with W = 0 at its schedule start (1, and lam_f for the
+    way back), which is prepended to its log; a log read from the library
+    holds its first row one logging interval after the start, so pass lam_f.
+    lam_f = None takes the backward log's first point as its start (a log
+    that already holds the start).  W(lambda->1) is the backward total
+    minus the backward work done before reaching lambda.  Returns (T, G)."""
     lam = np.asarray(lam_grid, float)
-    lam_b = np.asarray(lam_bwd, float)
-    w_b = np.asarray(w_bwd, float)
-    wf = _work_along(np.r_[1.0, np.asarray(lam_fwd, float)], np.r_[0.0, np.asarray(w_fwd, float)], lam)
+    lf, wfl = np.asarray(lam_fwd, float), np.asarray(w_fwd, float)
+    lam_b, w_b = np.asarray(lam_bwd, float), np.asarray(w_bwd, float)
+    wf = _work_along(*_with_start(1.0, lf, wfl), lam)
     wb_total = float(w_b[-1])
-    wb_before = _work_along(np.r_[lam_b[0] if len(lam_b) else 1.0, lam_b], np.r_[0.0, w_b], lam)
+    b_start = float(lam_f) if lam_f is not None else (float(lam_b[0]) if len(lam_b) else 1.0)
+    wb_before = _work_along(*_with_start(b_start, lam_b, w_b), lam)
     wb = wb_total - wb_before
     G = G0 / lam + 1.5 * n_atoms * KB * T0 * np.log(lam) / lam + (wf - wb) / (2.0 * lam)
     return T0 / lam, G
 
 
-def gibbs_as(G0: float, p_fwd, w_fwd, p_bwd, w_bwd, p_grid) -> Tuple[np.ndarray, np.ndarray]:
+def gibbs_as(G0: float, p_fwd, w_fwd, p_bwd, w_bwd, p_grid, p0=None, p1=None) -> Tuple[np.ndarray, np.ndarray]:
     """Gibbs free energy G(P, T) on p_grid from pressure switching (eq.
     Gibbs_AS): G0 + [W(P0->P) - W(P->P0)] / 2, with W = int dP/dt V dt (eq.
     Wmech_dyn) logged along the forward run P0 -> P1 and the backward run
     P1 -> P0 (pressures in the units of the work's P V, e.g. eV/A^3 with V
-    in A^3).  Returns (P, G)."""
+    in A^3).  Each run starts with W = 0 at its schedule start (p0 forward,
+    p1 backward), prepended to its log; pass both with library logs, whose
+    first row comes one logging interval after the start.  None takes the
+    log's first point as the start (a log that already holds it).
+    Returns (P, G)."""
     p = np.asarray(p_grid, float)
-    pb = np.asarray(p_bwd, float)
-    wb = np.asarray(w_bwd, float)
-    p0 = float(np.asarray(p_fwd, float)[0])
-    wf = _work_along(np.r_[p0, np.asarray(p_fwd, float)], np.r_[0.0, np.asarray(w_fwd, float)], p)
-    wb_before = _work_along(np.r_[pb[0], pb], np.r_[0.0, wb], p)
+    pf, wfl = np.asarray(p_fwd, float), np.asarray(w_fwd, float)
+    pb, wb = np.asarray(p_bwd, float), np.asarray(w_bwd, float)
+    f_start = float(p0) if p0 is not None else float(pf[0])
+    b_start = float(p1) if p1 is not None else float(pb[0])
+    wf = _work_along(*_with_start(f_start, pf, wfl), p)
+    wb_before = _work_along(*_with_start(b_start, pb, wb), p)
     return p, G0 + 0.5 * (wf - (float(wb[-1]) - wb_before))
 
 

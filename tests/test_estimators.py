@@ -160,3 +160,31 @@ def test_transition_temperature_and_liquid_assembly():
     assert g(g1, h1) == pytest.approx(g(g2, h2), abs=1e-12)
     F = est.liquid_free_energy(100, 2000.0, T, 28.0855, [1.0], [-0.8], [-3.0], [3.4])
     assert F == pytest.approx(est.ideal_gas_free_energy(100, 2000.0, T, 28.0855) + 0.9 - (-3.2))
+
+
+def test_gibbs_estimators_with_logs_that_skip_the_start():
+    """Logs read from the library hold their first row one logging interval
+    after the schedule start, not the start itself.  Given the schedule starts,
+    the estimators anchor W = 0 there: the ideal-gas G(P) and the harmonic
+    G(T) come out as from logs that hold the start, while anchoring at the
+    first logged row would be off by the work of one interval."""
+    N, T, P0, P1, n, every = 100, 800.0, 0.01, 0.05, 20000, 500
+    pf = np.linspace(P0, P1, n + 1)
+    wf = N * KB * T * np.log(pf / P0)
+    pb = pf[::-1]
+    wb = N * KB * T * np.log(pb / P1)
+    grid = np.linspace(P0, P1, 9)
+    rows = slice(every, None, every)          # rows after every `every` steps
+    _, G = est.gibbs_as(-3.0, pf[rows], wf[rows], pb[rows], wb[rows], grid, p0=P0, p1=P1)
+    exact = -3.0 + N * KB * T * np.log(grid / P0)
+    np.testing.assert_allclose(G, exact, atol=2e-3)
+    _, G_bad = est.gibbs_as(-3.0, pf[rows], wf[rows], pb[rows], wb[rows], grid)
+    assert np.abs(G_bad - exact).max() > 10 * np.abs(G - exact).max()
+
+    N, T0, c, lam_f = 64, 600.0, 5.0e4, 2.5
+    F = lambda T: 3 * N * KB * T * np.log(c / T)
+    lf, wfl, lb, wbl = _rs_harmonic_paths(N, T0, lam_f, 4001)
+    rows = slice(100, None, 100)
+    lam_grid = np.linspace(1.0, lam_f, 13)
+    T, G = est.gibbs_rs(F(T0), N, T0, lf[rows], wfl[rows], lb[rows], wbl[rows], lam_grid, lam_f=lam_f)
+    np.testing.assert_allclose(G, F(T), atol=2e-3)

@@ -260,3 +260,18 @@ def test_uf_minimum_image_equals_explicit_images():
     b = orc.uf_eval(x, box, UF["p"], UF["sigma"], UF["T"], 7.0, force_images=True)
     assert a["E"] == pytest.approx(b["E"], rel=1e-13)
     assert np.allclose(a["F"], b["F"], atol=1e-12)
+
+
+def test_thread_count_changes_no_result(sw_params):
+    """The neighbour search may run on several threads; each atom's list is
+    built alone and in the same order, so every output is bitwise the same."""
+    x, box = inputs.liquid_rsa(700, inputs.rng(990, 0, 0))
+    out = []
+    for n in (1, 4):
+        orc.set_threads(n)
+        out.append(orc.sw_eval(x, box, sw_params))
+    orc.set_threads(1)
+    a, b = out
+    assert a["E2"] == b["E2"] and a["E3"] == b["E3"]
+    for k in ("F", "virial", "dtheta", "e_atom", "nnb"):
+        assert np.array_equal(a[k], b[k]), k
