@@ -293,6 +293,32 @@ int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)
 int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_atom,
                         int64_t *list_entries, void *stream);
 
+/* ---- force evaluation that allocates nothing -------------------------------
+ * For callers that cannot allocate device or host memory during the call
+ * (tight serving loops, harnesses that forbid hipMalloc).  The Stillinger-
+ * Weber energy, forces and virial of n_sys (1..64) systems, as
+ * swfe_init_system followed by swfe_compute_forces with flags 0 would give
+ * them for force-only systems (mode, schedule, thermostat and barostat fields
+ * of d are ignored; offsets must be contiguous), bitwise for the same
+ * precision.  Scratch space is a library array of 32 MiB in device memory
+ * per GPU (held from its first use on that GPU until the process ends),
+ * enough for about 35 000 atoms; larger inputs are rejected with
+ * SWFE_E_NOMEM before any work is enqueued.  The call allocates nothing: no
+ * hipMalloc or hipFree, and only fixed-size host tables on the stack.
+ *   x      device [3][n_total] positions (caller owned, read only)
+ *   f      device [3][n_total] out: forces
+ *   e_atom device [n_total] out: per-atom energies, or NULL
+ *   out    device [n_sys][SWFE_OUT_STRIDE] out: E, 0 (no reference), dE/dstrain
+ *          (9), 0 (no parameter gradient), or NULL
+ * Work goes to `stream`; the call synchronises it before returning (device
+ * errors are reported: overflow, non-finite).  Every call on one GPU uses
+ * that GPU's one scratch array and leaves its contents behind: calls that
+ * overlap on the same GPU (other threads or streams) race and must be
+ * serialised by the caller.  Messages of failing calls come from
+ * swfe_last_error(NULL). */
+int swfe_forces_static(const swfe_system_desc *d, int32_t n_sys, const swfe_sw_params *p, const double *x,
+                       double *f, double *e_atom, double *out, int32_t precision, void *stream);
+
 /* ---- checkpoint / resume ---------------------------------------------------
  * A checkpoint is a host byte blob holding the context's settings (SW
  * parameters, descriptors with their current schedules, seed, time step,

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -77,8 +78,8 @@ struct swfe_ctx {
 
 namespace {
 
-// Message of the last failing call without a context (swfe_workspace_bytes),
-// returned by swfe_last_error(NULL).  A fixed buffer:
+// Message of the last failing call without a context (swfe_workspace_bytes,
+// swfe_forces_static), returned by swfe_last_error(NULL).  A fixed buffer:
 // recording it allocates nothing.
 char g_free_err[256] = "";
 
@@ -1071,6 +1072,107 @@ int swfe_neighbor_stats(swfe_ctx *ctx, int64_t *total_pairs, int32_t *max_per_at
 }
 
 }  // extern "C"
+
+// ---- force evaluation without allocation ------------------------------------
+// Library scratch of swfe_forces_static: one array per GPU, held from the
+// library's first use on that GPU until the process ends.  In host code the
+// name `scratch` is only a stand-in for the symbol; its device address on
+// each GPU comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kStaticMaxSys = 64;     // systems per call
+constexpr int kStaticMaxTiles = 1024; // tiles of kStaticBlock atoms per call
+constexpr int kStaticBlock = 256;     // block size (the contexts' default)
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_lock;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (taken on first use).
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIPCHK(nullptr, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, SWFE_E_INVALID_ARG, "device index beyond 63");
+    std::lock_guard<std::mutex> guard(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(nullptr, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(nullptr, SWFE_E_HIP, "hipGetSymbolAddress gave no address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SWFE_OK;
+}
+
+}  // namespace
+
+extern "C" int swfe_forces_static(const swfe_system_desc *d, int32_t n_sys, const swfe_sw_params *p,
+                                  const double *x, double *f, double *e_atom, double *out, int32_t precision,
+                                  void *stream)
+{
+    if (!d || !p || !x || !f) return fail(nullptr, SWFE_E_INVALID_ARG, "descriptors, parameters, x and f are required");
+    if (n_sys <= 0 || n_sys > kStaticMaxSys) return fail(nullptr, SWFE_E_INVALID_ARG, "n_sys must be in [1, 64]");
+    if (precision != SWFE_PREC_FP64 && precision != SWFE_PREC_MIXED)
+        return fail(nullptr, SWFE_E_INVALID_ARG, "precision must be SWFE_PREC_FP64 or SWFE_PREC_MIXED");
+    // every system is evaluated as a force-only system: the interaction alone
+    swfe_system_desc dd[kStaticMaxSys];
+    for (int i = 0; i < n_sys; ++i) {
+        memset(&dd[i], 0, sizeof dd[i]);
+        dd[i].n_atoms = d[i].n_atoms;
+        dd[i].offset = d[i].offset;
+        for (int k = 0; k < 3; ++k) dd[i].box[k] = d[i].box[k];
+        dd[i].mode = SWFE_MODE_FORCE;
+        dd[i].partner = -1;
+        dd[i].baro = SWFE_BARO_ISO;
+    }
+    SysDesc desc[kStaticMaxSys];
+    Group groups[kStaticMaxSys];
+    int n_groups = 0;
+    Plan P;  // scalars and layout only; its tables stay empty
+    RCHK(plan_core(nullptr, dd, n_sys, p, 0.001, kDefaultSkin, desc, groups, &n_groups, P));
+    if (P.lay.total > kStaticScratchBytes) {
+        char msg[200];
+        snprintf(msg, sizeof msg, "%lld atoms need %zu bytes of scratch; the static scratch holds %zu (about %lld atoms)",
+                 (long long)P.n_total, P.lay.total, kStaticScratchBytes,
+                 (long long)(kStaticScratchBytes / std::max<size_t>(1, P.lay.total / std::max<int64_t>(1, P.n_total))));
+        return fail(nullptr, SWFE_E_NOMEM, msg);
+    }
+    Tile tiles[kStaticMaxTiles];
+    const int nt = fill_tiles(desc, groups, n_groups, kStaticBlock, tiles, kStaticMaxTiles);
+    if (nt < 0) return fail(nullptr, SWFE_E_NOMEM, "more tiles than the static tables hold");
+    void *base = nullptr;
+    RCHK(scratch_address(&base));
+    hipStream_t s = (hipStream_t)stream;
+    DevPtrs q{};
+    q.x = const_cast<double *>(x);
+    q.f = f;
+    q.e_atom = e_atom;
+    q.out = out;
+    carve(q, (char *)base, P.lay);
+    SysState st[kStaticMaxSys];
+    initial_states(dd, n_sys, st);
+    const SwParams sw = make_sw(*p);
+    // the host tables are read by the copies before the stream is synchronised below
+    HIPCHK(nullptr, hipMemcpyAsync(q.state, st, sizeof(SysState) * n_sys, hipMemcpyHostToDevice, s));
+    HIPCHK(nullptr, hipMemcpyAsync((void *)q.desc, desc, sizeof(SysDesc) * n_sys, hipMemcpyHostToDevice, s));
+    HIPCHK(nullptr, hipMemcpyAsync((void *)q.tiles, tiles, sizeof(Tile) * nt, hipMemcpyHostToDevice, s));
+    HIPCHK(nullptr, hipMemcpyAsync((void *)q.groups, groups, sizeof(Group) * n_groups, hipMemcpyHostToDevice, s));
+    // the array keeps the last call's contents: the counters start at zero
+    HIPCHK(nullptr, launch_zero_words(q.cell_count, 4 * (size_t)P.cells, s));
+    HIPCHK(nullptr, launch_zero_words(q.disp_max, 8 * 2 * (size_t)n_sys, s));
+    const Ctl k = make_ctl_raw(desc, n_sys, nt, n_groups, P.n_total, 0.001, 0, P.list_cap, 0, 0, 1, 0, 0, nullptr);
+    HIPCHK(nullptr, launch_iota(k, q, kStaticBlock, s));
+    HIPCHK(nullptr, launch_reset_schedule(k, q, s));
+    HIPCHK(nullptr, enqueue_forces_raw(k, q, sw, precision == SWFE_PREC_MIXED, kStaticBlock, 2 | 4, s));
+    HIPCHK(nullptr, hipMemcpyAsync(st, q.state, sizeof(SysState) * n_sys, hipMemcpyDeviceToHost, s));
+    HIPCHK(nullptr, hipStreamSynchronize(s));
+    return device_error_status(nullptr, st, n_sys);
+}
 
 // ---- checkpoint / resume ----------------------------------------------------
 namespace {

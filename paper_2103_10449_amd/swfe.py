@@ -69,7 +69,7 @@ EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_byt
            "swfe_build_neighbors", "swfe_compute_forces", "swfe_set_schedule", "swfe_step_switched",
            "swfe_work_integral", "swfe_get_state", "swfe_set_log", "swfe_read_log", "swfe_set_block",
            "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats", "swfe_set_skin",
-           "swfe_set_params", "swfe_checkpoint_bytes", "swfe_save_state", "swfe_load_state")
+           "swfe_set_params", "swfe_checkpoint_bytes", "swfe_save_state", "swfe_load_state", "swfe_forces_static")
 KERNEL_NAMES = ("integrate", "rebuild_count", "rebuild_scan", "rebuild_scatter", "rebuild_order",
                 "rebuild_list", "pass1", "pass2", "finalize")
 
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.c_int),
         "swfe_set_skin": ([vp, ctypes.c_double, vp], ctypes.c_int),
         "swfe_set_params": ([vp, ctypes.POINTER(SwParams)], ctypes.c_int),
+        "swfe_forces_static": ([ctypes.POINTER(SystemDesc), i32, ctypes.POINTER(SwParams), vp, vp, vp, vp, i32, vp],
+                               ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -363,6 +365,24 @@ class Engine:
     def atom_energies(self, s: int = 0) -> np.ndarray:
         o, n = int(self.offsets[s]), self.counts[s]
         return self.e_atom[o:o + n].detach().cpu().numpy().copy()
+
+
+def forces_static(systems: Sequence, params: dict, x, f, e_atom=None, out=None, precision: str = "fp64"):
+    """swfe_forces_static: forces (and optionally per-atom energies and the
+    per-system rows E, -, dE/dstrain) of force-only systems into the caller's
+    device tensors x [3][n_total] (read), f [3][n_total], e_atom [n_total],
+    out [n_sys][20], with the library's static scratch (no allocation in the
+    call).  Synchronises torch's current stream."""
+    import torch
+    lib = load_library()
+    desc = system_descs(systems)
+    sw = sw_params_struct(params)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    rc = lib.swfe_forces_static(desc, len(systems), ctypes.byref(sw), ptr(x), ptr(f), ptr(e_atom), ptr(out),
+                                PREC_MIXED if precision == "mixed" else PREC_FP64, stream)
+    if rc != OK:
+        raise SwfeError(rc, lib.swfe_last_error(None).decode())
 
 
 # ---------------------------------------------------------------------------

@@ -136,3 +136,21 @@ def test_header_structs_match_binding(tmp_path):
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
+
+def test_static_forces_reject_oversized_input_before_any_gpu_work(swfe, sw_params):
+    """swfe_forces_static checks its input against the static scratch before
+    it touches the GPU: a 39304-atom system is refused with SWFE_E_NOMEM and
+    a message (the device pointers are not dereferenced)."""
+    xl, box = inputs.diamond((17, 17, 17), 5.431)
+    s = inputs.SystemSpec(x=xl, v=np.zeros_like(xl), box=box, mode=inputs.MODE_FORCE)
+    lib = swfe.load_library()
+    dummy = ctypes.c_void_p(16)
+    rc = lib.swfe_forces_static(swfe.system_descs([s]), 1, ctypes.byref(swfe.sw_params_struct(sw_params)),
+                                dummy, dummy, None, None, swfe.PREC_FP64, None)
+    assert rc == swfe.E_NOMEM
+    assert b"static scratch" in lib.swfe_last_error(None)
+    x, box = inputs.diamond((1, 1, 1), 5.431)
+    s = inputs.SystemSpec(x=x, v=np.zeros_like(x), box=box, mode=inputs.MODE_FORCE)
+    rc = lib.swfe_forces_static(swfe.system_descs([s]), 1, ctypes.byref(swfe.sw_params_struct(sw_params)),
+                                dummy, dummy, None, None, swfe.PREC_FP64, None)
+    assert rc == swfe.E_BOX_TOO_SMALL
