@@ -232,7 +232,12 @@ int swfe_set_schedule(swfe_ctx *ctx, const swfe_system_desc *d, void *stream);
  * shared lambda and P_S from both phases' instantaneous per-atom energy and
  * volume (section 3, eqs. Ps_coex_discreted and l_coex_discreted).  After a
  * SWFE_STRAIN force evaluation the interaction is first evaluated again at
- * the unstrained positions (f is overwritten).  use_graph != 0 replays one captured step graph.  Errors raised
+ * the unstrained positions (f is overwritten).  use_graph selects how the
+ * steps are launched, with identical results: 0 one launch per stage, 1 one
+ * captured step graph replayed per step, 2 one persistent cooperative kernel
+ * per (up to) 2000 steps, in which the systems are dealt to the XCDs and the
+ * workgroups of an XCD meet at barriers of their own (SWFE_E_HIP if the
+ * kernel cannot be launched, or if it had to give up a wait).  use_graph != 0 replays one captured step graph.  Errors raised
  * on the device (overflow, non-finite, dCCI singular, box too small) are
  * reported by the next synchronising call. */
 int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *stream);
@@ -283,7 +288,10 @@ int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream);
  * durations of integrate, rebuild count (with the rebuild decision),
  * rebuild scan, rebuild scatter,
  * rebuild order, rebuild list, pass1, pass2 and finalize (ms, host array of
- * 9).  Synchronises.  The steps advance the systems like swfe_step_switched. */
+ * 9).  When every system's cell table fits in LDS the first four rebuild
+ * stages run as one fused sort per system, whose time the count entry holds
+ * (scan, scatter and order then read 0).  Synchronises.  The steps advance
+ * the systems like swfe_step_switched. */
 #define SWFE_NUM_KERNELS 9
 int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream);
 

@@ -26,13 +26,15 @@ constexpr double kGpa = 1.602176634e-19 / 1e-30 / 1e9;                  // GPa p
 constexpr int kLogCapMax = 16384;                                       // rows of the log ring
 constexpr size_t kAlign = 256;
 constexpr double kDefaultSkin = 0.5;                                    // A
+constexpr int64_t kPersistChunk = 2000;  // steps of one persistent launch
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t xs, vs, fs, x0s, xb, txs, tvs, tfs, tx0s, zs, xf, fref;
     size_t perm, tperm, norder, rank, cellid, nnb, sl, cell_count, cell_start, nl, nl_cnt, mom, e_s;
-    size_t part1, part2, disp_max, work, n_work, desc, state, tiles, groups, log, strain, total;
+    size_t part1, part2, disp_max, work, n_work, desc, state, tiles, groups, log, strain;
+    size_t xtiles, xtloc, xgroups, xsys, sync, total;
 };
 
 struct Plan {
@@ -74,6 +76,10 @@ struct swfe_ctx {
     // the last force evaluation was strained: forces, energies and virial
     // belong to the strained box until the interaction is evaluated again
     bool forces_stale = false;
+    // persistent step kernel: systems dealt to the XCDs, and its grid
+    XcdPlan xplan{};
+    bool xplan_valid = false;
+    int persist_grid = 0;
 };
 
 namespace {
@@ -312,6 +318,11 @@ int plan_core(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw
     L.groups = take(sizeof(Group) * (size_t)ng);
     L.log = take(8 * (size_t)kLogCapMax * SWFE_LOG_STRIDE);
     L.strain = take(8 * 3 * (size_t)n_sys);
+    L.xtiles = take(4 * (size_t)tiles);
+    L.xtloc = take(4 * (size_t)tiles);
+    L.xgroups = take(4 * (size_t)n_sys);
+    L.xsys = take(4 * (size_t)n_sys);
+    L.sync = take(8 * (size_t)kSyncWords);
     L.total = o;
     return SWFE_OK;
 }
@@ -407,6 +418,11 @@ void carve(DevPtrs &q, char *w, const Layout &L)
     q.tiles = (const Tile *)(w + L.tiles);
     q.groups = (const Group *)(w + L.groups);
     q.log = (double *)(w + L.log);
+    q.xtiles = (int32_t *)(w + L.xtiles);
+    q.xtloc = (int32_t *)(w + L.xtloc);
+    q.xgroups = (int32_t *)(w + L.xgroups);
+    q.xsys = (int32_t *)(w + L.xsys);
+    q.sync = (unsigned long long *)(w + L.sync);
 }
 
 // Fresh per-system state of a set-up: boxes from the descriptors, no strain,
@@ -446,6 +462,11 @@ Ctl make_ctl_raw(const SysDesc *desc, int n_sys, int n_tiles, int n_groups, int6
         k.list16 &= desc[i].n <= 65536 ? 1 : 0;
         k.has_uf |= desc[i].mode == MODE_UF ? 1 : 0;
     }
+    // the fused sort keeps each system's cell table (at most cell_cap + 1
+    // entries) in LDS when every system's fits
+    int max_cells = 0;
+    for (int i = 0; i < n_sys; ++i) max_cells = std::max(max_cells, desc[i].cell_cap + 1);
+    k.sort_cells = max_cells <= kSortLdsCells ? max_cells : 0;
     k.in_step = in_step;
     k.force_rebuild = force_rebuild;
     k.log_every = log_every;
@@ -510,6 +531,88 @@ void drop_graph(swfe_ctx *c)
     c->gexec = nullptr;
     c->graph = nullptr;
     c->graph_valid = false;
+    c->xplan_valid = false;
+}
+
+// The systems dealt to the 8 XCDs for the persistent step kernel: whole
+// reduction groups, costliest first to the XCD with the least cost so far
+// (an atom costs kFxBase plus its neighbours within rc at the last pass 1).
+// Writes the per-XCD tile, group and system lists to the workspace and
+// picks the grid (the same number of workgroups for every XCD, no more than
+// fit at once, nor more than the largest tile list).  Synchronises.
+int build_xcd_plan(swfe_ctx *c, hipStream_t s)
+{
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::vector<int32_t> nn((size_t)c->n_total);
+    HIPCHK(c, hipMemcpy(nn.data(), c->ptrs.nnb, nn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int ng = (int)c->plan.groups.size();
+    std::vector<int64_t> gcost(ng, 0);
+    for (int g = 0; g < ng; ++g) {
+        const Group &G = c->plan.groups[g];
+        for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
+            const SysDesc &d = c->plan.desc[q == 0 ? G.s0 : G.s1];
+            for (int64_t a = d.off; a < d.off + d.n; ++a)
+                gcost[g] += kFxBase + std::min(std::max(nn[(size_t)a], 0), kMaxShort);
+        }
+    }
+    std::vector<int> order(ng);
+    for (int g = 0; g < ng; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gcost[a] > gcost[b]; });
+    std::vector<int64_t> load(kXcds, 0);
+    std::vector<std::vector<int>> owned(kXcds);
+    for (int g : order) {
+        int x = 0;
+        for (int y = 1; y < kXcds; ++y)
+            if (load[y] < load[x]) x = y;
+        owned[x].push_back(g);
+        load[x] += gcost[g];
+    }
+    std::vector<int32_t> xtiles, xtloc, xgroups, xsys;
+    XcdPlan xp{};
+    int max_tiles = 1;
+    for (int x = 0; x < kXcds; ++x) {
+        std::sort(owned[x].begin(), owned[x].end());
+        xp.tile_off[x] = (int32_t)xtiles.size();
+        xp.group_off[x] = (int32_t)xgroups.size();
+        xp.sys_off[x] = (int32_t)xsys.size();
+        for (int g : owned[x]) {
+            const Group &G = c->plan.groups[g];
+            xgroups.push_back(g);
+            for (int q = 0; q < (G.s1 >= 0 ? 2 : 1); ++q) {
+                const int sys = q == 0 ? G.s0 : G.s1;
+                const SysDesc &d = c->plan.desc[sys];
+                const int local = (int)xsys.size() - xp.sys_off[x];
+                xsys.push_back(sys);
+                for (int t = d.tile_begin; t < d.tile_end; ++t) {
+                    xtiles.push_back(t);
+                    xtloc.push_back(local);
+                }
+            }
+        }
+        const int nt = (int)xtiles.size() - xp.tile_off[x], nsx = (int)xsys.size() - xp.sys_off[x];
+        if (nsx > kPersistMaxSysPerXcd)
+            return fail(c, SWFE_E_INVALID_ARG, "persistent step: more than 256 systems on one XCD");
+        if (nt > kLdsShort * c->block - 1)
+            return fail(c, SWFE_E_INVALID_ARG, "persistent step: too many tiles on one XCD for the list stage's table");
+        max_tiles = std::max(max_tiles, nt);
+    }
+    xp.tile_off[kXcds] = (int32_t)xtiles.size();
+    xp.group_off[kXcds] = (int32_t)xgroups.size();
+    xp.sys_off[kXcds] = (int32_t)xsys.size();
+    HIPCHK(c, hipMemcpy(c->ptrs.xtiles, xtiles.data(), 4 * xtiles.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ptrs.xtloc, xtloc.data(), 4 * xtloc.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ptrs.xgroups, xgroups.data(), 4 * xgroups.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ptrs.xsys, xsys.data(), 4 * xsys.size(), hipMemcpyHostToDevice));
+    int dev = 0, cus = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int bpc = persist_blocks_per_cu(c->mixed, c->block);
+    if (bpc <= 0 || cus < kXcds) return fail(c, SWFE_E_HIP, "persistent step: no occupancy for the step kernel");
+    const int per_xcd = std::max(1, std::min(bpc * (cus / kXcds), max_tiles));
+    c->persist_grid = kXcds * per_xcd;
+    c->xplan = xp;
+    c->xplan_valid = true;
+    return SWFE_OK;
 }
 
 int upload_tables(swfe_ctx *c, hipStream_t s)
@@ -585,12 +688,15 @@ int device_error_status(swfe_ctx *c, const SysState *st, int n_sys)
         }
     if (!bits) return SWFE_OK;
     char msg[200];
-    const char *what = (bits & ERR_NONFINITE) ? "non-finite value"
+    const char *what = (bits & ERR_PERSIST) ? "persistent step kernel gave up a wait (a barrier timed out or an XCD "
+                                              "owning systems had no workgroup); the call's results are invalid"
+                       : (bits & ERR_NONFINITE) ? "non-finite value"
                        : (bits & ERR_OVERFLOW) ? "neighbour list overflow (list or short-list capacity exceeded)"
                        : (bits & ERR_BOX) ? "box length fell below twice the cutoff"
                                           : "dCCI update singular (|dv| or denominator too small, or lambda out of (0.05, 20))";
     snprintf(msg, sizeof msg, "system %d: %s", who, what);
-    int code = (bits & ERR_NONFINITE) ? SWFE_E_NONFINITE
+    int code = (bits & ERR_PERSIST) ? SWFE_E_HIP
+               : (bits & ERR_NONFINITE) ? SWFE_E_NONFINITE
                : (bits & ERR_OVERFLOW) ? SWFE_E_OVERFLOW
                : (bits & ERR_BOX) ? SWFE_E_BOX_TOO_SMALL
                                   : SWFE_E_DCCI_SINGULAR;
@@ -815,12 +921,22 @@ int swfe_step_switched(swfe_ctx *ctx, int64_t n_steps, int32_t use_graph, void *
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     if (n_steps < 0) return fail(ctx, SWFE_E_INVALID_ARG, "n_steps < 0");
     if (n_steps == 0) return SWFE_OK;
+    if (use_graph < 0 || use_graph > 2) return fail(ctx, SWFE_E_INVALID_ARG, "use_graph must be 0, 1 or 2");
     hipStream_t s = (hipStream_t)stream;
     RCHK(refresh_forces(ctx, s));
+    if (use_graph == 2 && !ctx->xplan_valid) RCHK(build_xcd_plan(ctx, s));
     Ctl k = make_ctl(ctx, 1, 0, 0);
     HIPCHK(ctx, launch_gather(k, ctx->ptrs, ctx->block, 1, s));
     HIPCHK(ctx, launch_begin_step(k, ctx->ptrs, ctx->sw, n_steps, s));
-    if (!use_graph) {
+    if (use_graph == 2) {
+        // launches of at most kPersistChunk steps, each from a cleared barrier area
+        for (int64_t done = 0; done < n_steps; done += kPersistChunk) {
+            const int64_t m = std::min<int64_t>(kPersistChunk, n_steps - done);
+            HIPCHK(ctx, launch_zero_words(ctx->ptrs.sync, 8 * (size_t)kSyncWords, s));
+            HIPCHK(ctx, launch_persist(k, ctx->ptrs, ctx->sw, ctx->xplan, ctx->mixed, ctx->block,
+                                       ctx->persist_grid, m, s));
+        }
+    } else if (!use_graph) {
         for (int64_t i = 0; i < n_steps; ++i) RCHK(enqueue_step(ctx, s));
     } else {
         if (!ctx->graph_valid) {

@@ -10,8 +10,13 @@ namespace swfe {
 constexpr int kMaxList = 64;       // Verlet-list capacity per atom without UF systems
 constexpr int kMaxListUF = 1024;   // largest capacity a UF reference may ask for
 constexpr int kMaxShort = 48;      // neighbours within rc per atom (pass 1 -> pass 2)
+// short-list entries pass 1 keeps in LDS per atom (the rest, rarely any, in
+// the global short list): its term loop reads them without a round trip to
+// memory
+constexpr int kLdsShort = 24;
 constexpr int kFxChunks = 4;      // runs of tiles per XCD (block placement)
 constexpr int kSortThreads = 1024; // threads of the per-system sort workgroup
+constexpr int kSortLdsCells = 12288; // cell table entries the fused sort keeps in LDS (48 KB)
 constexpr int kNumKernels = 9;     // launches of one dynamics step (for profiling)
 constexpr int kRebuildStages = 5;  // rebuild stages
 constexpr int kWorkGrid = 512;     // blocks of the work-list rebuild kernels
@@ -138,6 +143,8 @@ struct Ctl {
     int32_t in_step;        // 1: the pass belongs to a dynamics step
     int32_t force_rebuild;  // 1: rebuild every system's list now
     int32_t log_every, log_cap;
+    int32_t sort_cells;     // LDS cell-table entries of the fused sort (0: separate stages)
+    int32_t pad_;
     // The tiles are cut into 8 * kFxChunks runs of fx_len tiles; XCD x runs
     // the runs fx_chunk[x * kFxChunks + j], j < kFxChunks.
     int32_t fx_chunk[8 * kFxChunks];

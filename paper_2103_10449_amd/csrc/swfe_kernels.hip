@@ -255,6 +255,7 @@ __global__ void __launch_bounds__(256) k_iota(Ctl c, DevPtrs p)
 // Caller arrays (original order, [3][N]) -> sorted internal arrays.
 __global__ void __launch_bounds__(256) k_gather(Ctl c, DevPtrs p, int with_f)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.n_work[0] = 0;
     const int ti = tile_of_block(c);
     if (ti < 0) return;
     const Tile tile = p.tiles[ti];
@@ -401,8 +402,11 @@ __device__ __forceinline__ void integrate_tile(const Ctl &c, const DevPtrs &p, c
                   (unsigned long long)__double_as_longlong(dmax));
 }
 
+// Every launch sequence that may rebuild lists starts with integrate or
+// gather, which empty the rebuild work list for it.
 __global__ void __launch_bounds__(256) k_integrate(Ctl c, DevPtrs p, SwParams sw)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.n_work[0] = 0;
     const int ti = tile_of_block(c);
     if (ti >= 0) integrate_tile(c, p, sw, ti);
 }
@@ -575,6 +579,115 @@ __global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
 {
     const int n_work = p.n_work[0];
     for (int w = blockIdx.x; w < n_work; w += gridDim.x) rb_order_tile(p, p.work[w]);
+}
+
+// Rebuild stages 0-3 fused, one workgroup of kSortThreads per system (used
+// when every system's cell table fits in LDS, c.sort_cells entries): the
+// rebuild decision; for a stale list the cell of each atom and its rank among
+// the atoms counted into that cell (LDS counters), the exclusive scan of the
+// counts into cell starts (kept in LDS, written out for the list stage), the
+// atoms staged into their cells' segments, and their final order inside a
+// cell by caller index.  The system's tiles go to the list stage's work list.
+// The atoms come out in the same order as through the separate stages.
+__global__ void __launch_bounds__(kSortThreads) k_rb_sort(Ctl c, DevPtrs p, SwParams sw)
+{
+    extern __shared__ int32_t lcell[];  // counts, then starts: nc + 1 entries
+    __shared__ int rb_s, at_s;
+    __shared__ int32_t part[kSortThreads];
+    const int sys = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+    SysState &st = p.state[sys];
+    const SysDesc &d = p.desc[sys];
+    double box[3], ibox[3];
+    int nc3[3];
+    eff_box(st, box, ibox);
+    cell_grid(d, box, list_radius(sw, d), nc3);
+    const int nc = nc3[0] * nc3[1] * nc3[2];
+    const int off = (int)d.off, n = (int)d.n;
+    if (tid == 0) {
+        const bool rb = list_stale(c, p, sw, sys);
+        // clear the slot the next step's integrate fills (both on a forced build)
+        p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
+        if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
+        rb_s = rb ? 1 : 0;
+        at_s = rb ? atomicAdd(&p.n_work[0], d.tile_end - d.tile_begin) : 0;
+    }
+    __syncthreads();
+    if (!rb_s) return;
+    for (int q = tid; q < d.tile_end - d.tile_begin; q += nth) p.work[at_s + q] = d.tile_begin + q;
+    for (int q = tid; q <= nc; q += nth) lcell[q] = 0;
+    __syncthreads();
+    // cell of every atom and its rank among the atoms counted into the cell
+#pragma unroll 4
+    for (int a = tid; a < n; a += nth) {
+        const int t = off + a;
+        const int cell = cell_of_pos(p.xs[t], ibox, nc3);
+        p.cellid[t] = cell;
+        p.rank[t] = atomicAdd(&lcell[cell], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the counts into starts (sorted positions)
+    const int per = (nc + nth - 1) / nth;
+    const int lo = min(tid * per, nc), hi = min(lo + per, nc);
+    int sum = 0;
+    for (int q = lo; q < hi; ++q) sum += lcell[q];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < nth; o <<= 1) {
+        const int add = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+    }
+    int32_t *start = p.cell_start + d.cell_base + sys;  // nc + 1 entries
+    int run = off + part[tid] - sum;
+    for (int q = lo; q < hi; ++q) {
+        const int v = lcell[q];
+        lcell[q] = run;
+        start[q] = run;
+        run += v;
+    }
+    if (tid == 0) {
+        lcell[nc] = off + n;
+        start[nc] = off + n;
+    }
+    __syncthreads();
+    // atom data into its cell's segment of the staging arrays (by rank)
+#pragma unroll 4
+    for (int a = tid; a < n; a += nth) {
+        const int t = off + a;
+        const int cell = p.cellid[t];
+        const int s = lcell[cell] + p.rank[t];
+        p.txs[s] = p.xs[t];
+        p.tvs[s] = p.vs[t];
+        p.tfs[s] = p.fs[t];
+        if (p.x0) p.tx0s[s] = p.x0s[t];
+        p.tperm[s] = p.perm[t];
+        p.norder[s] = cell;
+    }
+    __syncthreads();
+    // final order: inside a cell atoms follow the caller's atom index
+    for (int a = tid; a < n; a += nth) {
+        const int i = off + a;
+        const int cell = p.norder[i];
+        const int b = lcell[cell], e = lcell[cell + 1];
+        const int key = p.tperm[i];
+        int rank = 0;
+#pragma unroll 4
+        for (int j = b; j < e; ++j) rank += p.tperm[j] < key ? 1 : 0;
+        const int s = b + rank;
+        const double4 x = p.txs[i];
+        p.xs[s] = x;
+        p.xf[s] = pos_f32(x, box, ibox);
+        p.xb[s] = make_dvec3(x.x, x.y, x.z);
+        p.vs[s] = p.tvs[i];
+        p.fs[s] = p.tfs[i];
+        if (p.x0) p.x0s[s] = p.tx0s[i];
+        p.perm[s] = key;
+    }
+    if (tid == 0) {
+        for (int k = 0; k < 3; ++k) st.box_build[k] = box[k];
+        st.n_rebuild += 1;
+    }
 }
 
 // Verlet-list storage.  With 32-bit entries, entry k of sorted atom s is the
@@ -789,10 +902,6 @@ struct Fm<double> {
 // Gather batch sizes: list candidates (filter), short-list neighbours in
 // pass 1 and in pass 2 (smaller where the registers are needed elsewhere).
 constexpr int kBatchA = 8;
-// short-list entries pass 1 keeps in LDS (the rest, rarely any, in the
-// global short list): the term loop then reads its neighbour indices without
-// a round trip to memory
-constexpr int kLdsShort = 24;
 template <typename R, bool GRAD>
 struct Batch {
     static constexpr int B = GRAD ? 2 : 4;
@@ -1260,28 +1369,33 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
         block_copy(&sst[q], &p.state[sid[q]], sizeof(SysState));
         block_copy(&sdesc[q], &p.desc[sid[q]], sizeof(SysDesc));
     }
+    // Four partial sums per slot, over the tiles of each residue mod 4, in
+    // rounds of sixteen independent loads in flight (the last one padded with
+    // zeros), then added in order: the same summation order whatever the
+    // block's wave count (a wave takes several residues when fewer than four).
+    constexpr int NJ = 4;
     const int k = threadIdx.x & 63, j = threadIdx.x >> 6, nj = blockDim.x >> 6;
     for (int q = 0; q < nq; ++q) {
         const SysDesc &d = p.desc[sid[q]];
-        double a = 0.0;
-        if (k < 2 * kNumPart) {
-            const double *src = k < kNumPart ? p.part1 + k : p.part2 + (k - kNumPart);
-            // rounds of sixteen independent loads in flight (the last one
-            // padded with zeros), summed in a fixed order
-            for (int t = d.tile_begin + j; t < d.tile_end; t += 16 * nj) {
-                double v[16];
+        for (int jj = j; jj < NJ; jj += nj) {
+            double a = 0.0;
+            if (k < 2 * kNumPart) {
+                const double *src = k < kNumPart ? p.part1 + k : p.part2 + (k - kNumPart);
+                for (int t = d.tile_begin + jj; t < d.tile_end; t += 16 * NJ) {
+                    double v[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    v[u] = t + u * nj < d.tile_end ? src[(int64_t)(t + u * nj) * kNumPart] : 0.0;
+                    for (int u = 0; u < 16; ++u)
+                        v[u] = t + u * NJ < d.tile_end ? src[(int64_t)(t + u * NJ) * kNumPart] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 16; ++u) a += v[u];
+                    for (int u = 0; u < 16; ++u) a += v[u];
+                }
             }
+            red[jj][k] = a;
         }
-        red[j][k] = a;
         __syncthreads();
         if (j == 0 && k < 2 * kNumPart) {
             double s = 0.0;
-            for (int w = 0; w < nj; ++w) s += red[w][k];
+            for (int w = 0; w < NJ; ++w) s += red[w][k];
             sums[q][k] = s;
         }
         __syncthreads();
@@ -1611,7 +1725,9 @@ __device__ bool xcd_barrier(unsigned long long *ctr, unsigned long long target, 
             add_agent(ctr, 1ull);
             ok = wait_at_least(ctr, target, abort_w);
         }
-        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        // device-scope invalidate: the CU's L1 (a group-scope invalidate
+        // leaves it when a workgroup is not split across CUs)
+        asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
         *flag_s = ok ? 1 : 0;
     }
     __syncthreads();
@@ -1792,6 +1908,13 @@ hipError_t launch_integrate(const Ctl &c, const DevPtrs &p, const SwParams &sw, 
 hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, int block, int stage,
                           hipStream_t s)
 {
+    if (c.sort_cells > 0 && stage < 4) {
+        // the fused sort does stages 0-3 in one launch
+        if (stage == 0)
+            hipLaunchKernelGGL(k_rb_sort, dim3(c.n_sys), dim3(kSortThreads), sizeof(int32_t) * (size_t)c.sort_cells,
+                               s, c, p, sw);
+        return hipGetLastError();
+    }
     switch (stage) {
         case 0: hipLaunchKernelGGL(k_rb_count, tile_grid(c), dim3(block), 0, s, c, p, sw); break;
         case 1: hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw); break;

@@ -272,8 +272,11 @@ class Engine:
         desc = system_descs(specs) if specs is not None else None
         self._check(self.lib.swfe_set_schedule(self.ctx, desc, self._stream()))
 
-    def step(self, n_steps: int, use_graph: bool = True):
-        self._check(self.lib.swfe_step_switched(self.ctx, int(n_steps), int(bool(use_graph)), self._stream()))
+    def step(self, n_steps: int, use_graph: bool = True, persistent: bool = False):
+        """n_steps switched steps: eager launches, a replayed step graph, or
+        (persistent=True) the persistent step kernel."""
+        mode = 2 if persistent else int(bool(use_graph))
+        self._check(self.lib.swfe_step_switched(self.ctx, int(n_steps), mode, self._stream()))
 
     def work_integral(self):
         W, lam, Ps = (np.zeros(self.n_sys) for _ in range(3))
