@@ -47,7 +47,7 @@ INTEGRATE_BYTES = 180
 INTEGRATE_BYTES_FL = 24
 PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
 PEAK_HBM = 8.0e12                             # B/s
-SKINS = (0.4, 0.7, 1.0, 1.4)  # Verlet skins tried during warm-up, A
+SKINS = (0.4, 0.7, 1.0, 1.4, 1.8)  # Verlet skins the autotuner tries with --skin 0, A
 REPEATS = 5                   # timed windows of K steps; the value is their median
 PEAK_FP32_NONPACKED = 78.6e12 # FP32 vector roof without packed FP32 instructions (the library's build)
 # Delta F gate: the switching protocol of the workload (1000 steps each way),
@@ -108,6 +108,46 @@ def kernel_flops(name, n_atoms, ordered_pairs):
     return None
 
 
+STEP_KERNELS = ("integrate", "rebuild_count", "rebuild_scan", "rebuild_scatter", "rebuild_order",
+                "rebuild_list", "pass1", "pass2", "finalize")
+
+
+def step_algorithmic_bytes(n_atoms, n_fl, pairs, list_entries, rebuilt_atoms, n_tiles, mom_bytes):
+    """Algorithmic HBM bytes of one dynamics step, per kernel: every per-atom
+    operand read or written once, neighbour data gathered from cache not
+    counted.  integrate as INTEGRATE_BYTES; pass 1: position (24), list count
+    (4), 16-bit list entries, moments written, short-list entries (2 per
+    pair) and count (4), pair force written (24); pass 2: position,
+    moments, short list and count, caller index (4), force and velocity
+    read and written (96), next normals written (24), Frenkel-Ladd anchors
+    (24); the rebuild stages per rebuilt atom: position, velocity, force and
+    anchor staged and placed (384) and 16-bit list entries (2 each, at the
+    batch's mean list length); finalize: both passes' tile partials."""
+    list_per_atom = list_entries / n_atoms
+    return {
+        "integrate": INTEGRATE_BYTES * n_atoms + INTEGRATE_BYTES_FL * n_fl,
+        "rebuild": rebuilt_atoms * (384 + 2 * list_per_atom),
+        "pass1": n_atoms * (24 + 4 + mom_bytes + 4 + 24) + 2 * list_entries + 2 * pairs,
+        "pass2": n_atoms * (24 + mom_bytes + 4 + 4 + 96 + 24) + 24 * n_fl + 2 * pairs,
+        "finalize": n_tiles * 2 * 26 * 8,
+    }
+
+
+def step_traffic(run, skin, replicas, precision, n_fl, mom_bytes):
+    """Whole-step HBM bytes from the counters (sum over the step's kernels of
+    the bytes per launch) against the algorithmic bytes of one step; None
+    when the counters were not taken on this configuration and sources."""
+    meas = {k: measured_traffic(k, skin, replicas, precision, run["block"]) for k in STEP_KERNELS}
+    if any(v is None for v in meas.values()):
+        return None
+    alg = step_algorithmic_bytes(run["n_atoms"], n_fl, run["pairs"], run["list_entries"],
+                                 run["rebuilt_atoms_per_step"], run["n_tiles"], mom_bytes)
+    counter = sum(meas.values())
+    total = sum(alg.values())
+    return {"counter_bytes": counter, "algorithmic_bytes": total, "ratio": counter / total,
+            "counter_bytes_per_kernel": meas, "algorithmic_bytes_per_kernel": alg}
+
+
 def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, skins=None, block=0):
     import torch
     from paper_2103_10449_amd import swfe
@@ -123,29 +163,22 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
         block = eng.autotune()
     print(f"# {precision}: engine ready, block {block}", file=sys.stderr, flush=True)
     starts = [(s.sched_start, s.sched_end) for s in specs]
-    # warm-up at the start of the path (lambda held); its first steps pick
-    # the Verlet skin (rebuild frequency vs list length) by timing
+    # warm-up at the start of the path (lambda held); with no skin given the
+    # library's autotuner picks it (rebuild frequency vs list length) by timing
     for s, (a, b) in zip(specs, starts):
         s.sched_start, s.sched_end, s.sched_steps = a, a, 0
     eng.set_schedule(specs)
-    best = None
-    for skin in (skins or SKINS):
+    if skins and len(skins) == 1:
+        skin = skins[0]
         eng.set_skin(skin)
-        eng.step(5, use_graph=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        eng.step(40, use_graph=True)
-        torch.cuda.synchronize()
-        dt_skin = time.perf_counter() - t0
-        if best is None or dt_skin < best[1]:
-            best = (skin, dt_skin)
-    eng.set_skin(best[0])
-    print(f"# {precision}: skin {best[0]} A", file=sys.stderr, flush=True)
+    else:
+        skin = eng.autotune_skin(skins or SKINS, steps=40)
+    print(f"# {precision}: skin {skin} A", file=sys.stderr, flush=True)
     eng.step(warmup, use_graph=True)
     torch.cuda.synchronize()
     eng.state()  # raises on a device error (non-finite, overflow, box)
     print(f"# {precision}: {warmup} warm-up steps done", file=sys.stderr, flush=True)
-    rb0 = sum(x["n_rebuild"] for x in eng.state())
+    rb0 = [x["n_rebuild"] for x in eng.state()]
     walls, gpus = [], []
     for rep in range(REPEATS):
         t_total = 0.0
@@ -167,14 +200,18 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
         walls.append(t_total)
         gpus.append(ev_total)
         print(f"# {precision}: window {rep}: {2 * half} steps in {t_total:.4f} s", file=sys.stderr, flush=True)
-    n_rebuild = sum(x["n_rebuild"] for x in eng.state()) - rb0
+    rb1 = [x["n_rebuild"] for x in eng.state()]
+    n_rebuild = sum(rb1) - sum(rb0)
+    rebuilt_atoms = sum((b - a) * sp.n for a, b, sp in zip(rb0, rb1, specs))
     eng.state()  # raises on a device error (non-finite, overflow, box)
     pairs, max_nb, list_entries = eng.neighbor_stats()
     prof = eng.profile_steps(profile_steps) if profile_steps else None
     eng.close()
     return dict(n_atoms=n_atoms, wall=float(np.median(walls)), walls=walls, gpu=float(np.median(gpus)),
-                steps=2 * half, block=block, skin=best[0], pairs=pairs, max_nb=max_nb, list_entries=list_entries,
-                rebuilds_per_step=n_rebuild / (REPEATS * 2 * half), prof=prof, n_rep=len(specs))
+                steps=2 * half, block=block, skin=skin, pairs=pairs, max_nb=max_nb, list_entries=list_entries,
+                rebuilds_per_step=n_rebuild / (REPEATS * 2 * half),
+                rebuilt_atoms_per_step=rebuilt_atoms / (REPEATS * 2 * half), prof=prof, n_rep=len(specs),
+                n_tiles=sum(-(-sp.n // block) for sp in specs))
 
 
 def _switch_both_ways(eng, specs, n_steps):
@@ -415,7 +452,7 @@ def main():
                     help="block size of the FP64 run (0: swfe_autotune)")
     ap.add_argument("--skin", type=float, default=1.4,
                     help="Verlet skin in A (default 1.4, the fastest of 0.4-1.8 A on this workload; "
-                         "0: choose among 0.4, 0.7, 1.0, 1.4 A by timing during warm-up)")
+                         "0: the library autotuner chooses among 0.4, 0.7, 1.0, 1.4, 1.8 A)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
@@ -494,7 +531,9 @@ def main():
             print(f"# Delta F gate: {json.dumps(out['dF_gate'])}", file=sys.stderr, flush=True)
     prof = mixed["prof"]
     if prof:
-        name = max(prof, key=prof.get)
+        # the longer force pass (the kernels with a flop model); the longest
+        # kernel of the step is reported beside it
+        name = max(("pass1", "pass2"), key=prof.get)
         n_prof = args.profile_steps
         avg = prof[name] / n_prof / 1e3              # s per launch
         fl = kernel_flops(name, mixed["n_atoms"], mixed["pairs"])
@@ -507,7 +546,8 @@ def main():
                            "traffic": traffic, "avg_launch_us": 1e6 * avg,
                            "hbm_GBps": traffic / avg / 1e9 if traffic else None,
                            "hbm_frac": traffic / avg / PEAK_HBM if traffic else None,
-                           "per_kernel_us": {k: 1e3 * v / n_prof for k, v in prof.items()}}
+                           "per_kernel_us": {k: 1e3 * v / n_prof for k, v in prof.items()},
+                           "longest_kernel": max(prof, key=prof.get)}
         if fp64 is not None and fp64["prof"]:
             p64 = fp64["prof"]
             avg64 = p64[name] / n_prof / 1e3
@@ -528,6 +568,8 @@ def main():
             out["roofline_integrate"] = {"bound": "hbm", "kernel": "integrate", "achieved": alg / avg_i / 1e9,
                                          "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": alg / avg_i / PEAK_HBM,
                                          "algorithmic_bytes": alg, "traffic": tr_i, "avg_launch_us": 1e6 * avg_i}
+        n_fl = sum(s.n for s in base.systems if s.mode == inputs.MODE_FL)
+        out["step_traffic"] = step_traffic(mixed, mixed["skin"], args.replicas, "mixed", n_fl, 36)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     if not args.no_per_config:

@@ -283,6 +283,17 @@ int swfe_sizes(const swfe_ctx *ctx, int64_t *n_total, int32_t *n_sys);
  * the current positions. */
 int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream);
 
+/* Tuning: Verlet-list skin.  Times n_steps graph-replayed dynamics steps
+ * (after 5 untimed ones; n_steps <= 0: 40) from the current state at each
+ * candidate skin (A; NULL: 0.6, 0.9, 1.2, 1.4, 1.7; at most 16), the faster
+ * of two interleaved rounds, restoring the state from a host snapshot after
+ * each (it allocates swfe_checkpoint_bytes of host memory for the call),
+ * and keeps the fastest (host output `chosen`).  A longer skin rebuilds the
+ * lists less often but makes them longer; results do not depend on it.
+ * Does not advance the dynamics. */
+int swfe_autotune_skin(swfe_ctx *ctx, const double *candidates, int32_t n_candidates, int32_t n_steps,
+                       double *chosen, void *stream);
+
 /* Measurement: run n_steps eager dynamics steps with HIP events recorded on
  * the stream between the kernels of each step; ms[0..8] receive the summed
  * durations of integrate, rebuild count (with the rebuild decision),

@@ -463,10 +463,15 @@ Ctl make_ctl_raw(const SysDesc *desc, int n_sys, int n_tiles, int n_groups, int6
         k.has_uf |= desc[i].mode == MODE_UF ? 1 : 0;
     }
     // the fused sort keeps each system's cell table (at most cell_cap + 1
-    // entries) in LDS when every system's fits
+    // entries) in LDS; it is used when every system's fits and every system
+    // is small
     int max_cells = 0;
-    for (int i = 0; i < n_sys; ++i) max_cells = std::max(max_cells, desc[i].cell_cap + 1);
-    k.sort_cells = max_cells <= kSortLdsCells ? max_cells : 0;
+    int64_t max_atoms = 0;
+    for (int i = 0; i < n_sys; ++i) {
+        max_cells = std::max(max_cells, desc[i].cell_cap + 1);
+        max_atoms = std::max(max_atoms, desc[i].n);
+    }
+    k.sort_cells = max_cells <= kSortLdsCells && max_atoms <= kSortFuseMaxAtoms ? max_cells : 0;
     k.in_step = in_step;
     k.force_rebuild = force_rebuild;
     k.log_every = log_every;
@@ -1122,6 +1127,55 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
         if (best_ms[q] <= 1.01f * fastest) best_b = cand[q];
     if (chosen_block) *chosen_block = best_b;
     return swfe_set_block(ctx, best_b, stream);
+}
+
+int swfe_autotune_skin(swfe_ctx *ctx, const double *candidates, int32_t n_candidates, int32_t n_steps,
+                       double *chosen, void *stream)
+{
+    if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
+    static const double kDefaultSkins[] = {0.6, 0.9, 1.2, 1.4, 1.7};
+    if (!candidates) {
+        candidates = kDefaultSkins;
+        n_candidates = (int32_t)(sizeof kDefaultSkins / sizeof kDefaultSkins[0]);
+    }
+    if (n_candidates <= 0 || n_candidates > 16) return fail(ctx, SWFE_E_INVALID_ARG, "1 to 16 skin candidates");
+    for (int q = 0; q < n_candidates; ++q)
+        if (!(candidates[q] >= 0.0 && candidates[q] < 5.0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be in [0, 5) A");
+    if (n_steps <= 0) n_steps = 40;
+    hipStream_t s = (hipStream_t)stream;
+    // every candidate steps the same state: a host snapshot is restored
+    // after each trial, so the call leaves the dynamics where they were
+    size_t bytes = 0;
+    RCHK(swfe_checkpoint_bytes(ctx, &bytes));
+    std::vector<char> snap(bytes);
+    RCHK(swfe_save_state(ctx, snap.data(), bytes, stream));
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    std::vector<float> best(n_candidates, 1e30f);
+    auto trial = [&](int q) -> int {
+        RCHK(swfe_set_skin(ctx, candidates[q], stream));
+        RCHK(swfe_step_switched(ctx, 5, 1, stream));  // capture and warm the step graph
+        HIPCHK(ctx, hipEventRecord(e0, s));
+        RCHK(swfe_step_switched(ctx, n_steps, 1, stream));
+        HIPCHK(ctx, hipEventRecord(e1, s));
+        HIPCHK(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+        best[q] = std::min(best[q], ms);
+        return swfe_load_state(ctx, snap.data(), bytes, stream);
+    };
+    int rc = SWFE_OK;
+    for (int round = 0; round < 2 && rc == SWFE_OK; ++round)
+        for (int q = 0; q < n_candidates && rc == SWFE_OK; ++q) rc = trial(q);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    int qb = 0;
+    for (int q = 1; q < n_candidates; ++q)
+        if (best[q] < best[qb]) qb = q;
+    if (chosen) *chosen = candidates[qb];
+    return swfe_set_skin(ctx, candidates[qb], stream);
 }
 
 int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream)

@@ -17,6 +17,11 @@ constexpr int kLdsShort = 24;
 constexpr int kFxChunks = 4;      // runs of tiles per XCD (block placement)
 constexpr int kSortThreads = 1024; // threads of the per-system sort workgroup
 constexpr int kSortLdsCells = 12288; // cell table entries the fused sort keeps in LDS (48 KB)
+// The fused sort puts a whole system on one workgroup: it pays off only when
+// every system of the batch is small (the separate stages spread a large
+// system's sort over the chip; measured on the 64-replica batch with systems
+// of up to 13 824 atoms, the fused sort became the longest kernel of a step).
+constexpr int kSortFuseMaxAtoms = 2048;
 constexpr int kNumKernels = 9;     // launches of one dynamics step (for profiling)
 constexpr int kRebuildStages = 5;  // rebuild stages
 constexpr int kWorkGrid = 512;     // blocks of the work-list rebuild kernels

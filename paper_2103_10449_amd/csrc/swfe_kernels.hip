@@ -1065,14 +1065,13 @@ __device__ __forceinline__ void pass1_tile(const Ctl &c, const DevPtrs &p, const
                 }
             }
         }
+        // the virial is symmetric: the tile partials hold its upper triangle
+        // (slots yx, zx, zy stay zero; finalize mirrors them)
         acc[1] = vxx;
         acc[2] = vxy;
         acc[3] = vxz;
-        acc[4] = vxy;
         acc[5] = vyy;
         acc[6] = vyz;
-        acc[7] = vxz;
-        acc[8] = vyz;
         acc[9] = vzz;
         // own three-body energy from the FP64 moments
         const double c0 = sw.cos0, omc = 1.0 - c0;
@@ -1306,13 +1305,23 @@ __device__ void step_factors(const SysDesc &d, SysState &st, double dt, double r
 {
     // velocities: dv_a/dt = F_a/m - (v_eps,a + tr v_eps / N_f) v_a; positions:
     // dx_a/dt = v_a + v_eps,a x_a; both exact over a half step
+    // (a zero rate gives factors of exactly 1, and equal rates equal
+    // factors: the exponentials are evaluated once per distinct axis rate)
     const double tr = st.veps[0] + st.veps[1] + st.veps[2];
     for (int a = 0; a < 3; ++a) {
         const double zk = d.baro ? (st.veps[a] + tr / d.nf) * 0.5 * dt : d.alpha * st.veps[a] * 0.5 * dt;
-        st.decay[a] = exp(-zk);
-        st.phi[a] = zk == 0.0 ? 1.0 : -expm1(-zk) / zk;
         const double za = st.veps[a] * 0.5 * dt;
-        st.grow[a] = exp(za);
+        if (a > 0 && zk == (d.baro ? (st.veps[a - 1] + tr / d.nf) * 0.5 * dt : d.alpha * st.veps[a - 1] * 0.5 * dt) &&
+            za == st.veps[a - 1] * 0.5 * dt) {
+            st.decay[a] = st.decay[a - 1];
+            st.phi[a] = st.phi[a - 1];
+            st.grow[a] = st.grow[a - 1];
+            st.psi[a] = st.psi[a - 1];
+            continue;
+        }
+        st.decay[a] = zk == 0.0 ? 1.0 : exp(-zk);
+        st.phi[a] = zk == 0.0 ? 1.0 : -expm1(-zk) / zk;
+        st.grow[a] = za == 0.0 ? 1.0 : exp(za);
         st.psi[a] = za == 0.0 ? 1.0 : expm1(za) / za;
     }
     if (d.mode != MODE_FORCE)
@@ -1412,6 +1421,9 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
             st.E3 = a[P_E3];
             st.U_int = st.E2 + st.E3;
             for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
+            st.vir[3] = st.vir[1];  // lower triangle from the upper one
+            st.vir[6] = st.vir[2];
+            st.vir[7] = st.vir[5];
             for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
             st.U_ref = b[P_UREF] + (d.mode == MODE_UF ? a[P_UUF] : 0.0);
             for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
@@ -1561,14 +1573,13 @@ __device__ __forceinline__ void pass2_tile(const Ctl &c, const DevPtrs &p, const
                 }
             }
         }
+        // the virial is symmetric: the tile partials hold its upper triangle
+        // (slots yx, zx, zy stay zero; finalize mirrors them)
         acc[1] = vxx;
         acc[2] = vxy;
         acc[3] = vxz;
-        acc[4] = vxy;
         acc[5] = vyy;
         acc[6] = vyz;
-        acc[7] = vxz;
-        acc[8] = vyz;
         acc[9] = vzz;
         if (GRAD) {
             const double hl = 0.5 * sw.le;
@@ -1724,10 +1735,11 @@ __device__ bool xcd_barrier(unsigned long long *ctr, unsigned long long target, 
         if (nb > 1) {
             add_agent(ctr, 1ull);
             ok = wait_at_least(ctr, target, abort_w);
+            // device-scope invalidate: the CU's L1 (a group-scope invalidate
+            // leaves it when a workgroup is not split across CUs).  A lone
+            // workgroup reads only what its own CU wrote and needs none.
+            asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
         }
-        // device-scope invalidate: the CU's L1 (a group-scope invalidate
-        // leaves it when a workgroup is not split across CUs)
-        asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
         *flag_s = ok ? 1 : 0;
     }
     __syncthreads();

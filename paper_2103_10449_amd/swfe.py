@@ -69,7 +69,8 @@ EXPORTS = ("swfe_create", "swfe_destroy", "swfe_last_error", "swfe_workspace_byt
            "swfe_build_neighbors", "swfe_compute_forces", "swfe_set_schedule", "swfe_step_switched",
            "swfe_work_integral", "swfe_get_state", "swfe_set_log", "swfe_read_log", "swfe_set_block",
            "swfe_autotune", "swfe_sizes", "swfe_profile_steps", "swfe_neighbor_stats", "swfe_set_skin",
-           "swfe_set_params", "swfe_checkpoint_bytes", "swfe_save_state", "swfe_load_state", "swfe_forces_static")
+           "swfe_set_params", "swfe_checkpoint_bytes", "swfe_save_state", "swfe_load_state", "swfe_forces_static",
+           "swfe_autotune_skin")
 KERNEL_NAMES = ("integrate", "rebuild_count", "rebuild_scan", "rebuild_scatter", "rebuild_order",
                 "rebuild_list", "pass1", "pass2", "finalize")
 
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.c_int),
         "swfe_set_skin": ([vp, ctypes.c_double, vp], ctypes.c_int),
         "swfe_set_params": ([vp, ctypes.POINTER(SwParams)], ctypes.c_int),
+        "swfe_autotune_skin": ([vp, dp, i32, i32, dp, vp], ctypes.c_int),
         "swfe_forces_static": ([ctypes.POINTER(SystemDesc), i32, ctypes.POINTER(SwParams), vp, vp, vp, vp, i32, vp],
                                ctypes.c_int),
     }
@@ -318,6 +320,15 @@ class Engine:
         b = ctypes.c_int32(0)
         self._check(self.lib.swfe_autotune(self.ctx, ctypes.byref(b), self._stream()))
         return int(b.value)
+
+    def autotune_skin(self, candidates=None, steps: int = 40) -> float:
+        """Pick the Verlet skin by timing graph steps at each candidate (the
+        library's autotuner); returns the chosen skin in A."""
+        c = None if candidates is None else np.ascontiguousarray(candidates, dtype=np.float64)
+        out = ctypes.c_double(0.0)
+        self._check(self.lib.swfe_autotune_skin(self.ctx, _dp(c), 0 if c is None else len(c), int(steps),
+                                                ctypes.byref(out), self._stream()))
+        return float(out.value)
 
     def profile_steps(self, n_steps: int) -> dict:
         """Per-kernel HIP-event durations (ms, summed over n_steps eager steps)."""

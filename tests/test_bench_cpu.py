@@ -77,3 +77,29 @@ def test_kernel_flops_count_each_unique_term_once():
     assert bench.kernel_flops("pass1", atoms, pairs) == pairs / 2 * bench.C_PAIR + pairs * bench.C_MOM
     assert bench.kernel_flops("pass2", atoms, pairs) == pairs * bench.C_D3 + atoms * bench.C_ATOM2
     assert bench.kernel_flops("integrate", atoms, pairs) is None
+
+
+def test_step_algorithmic_bytes_by_hand():
+    # 10 atoms (4 Frenkel-Ladd), 30 ordered pairs, 80 list entries, 5 atoms
+    # rebuilt per step, 2 tiles, FP32 moments
+    a = bench.step_algorithmic_bytes(10, 4, 30, 80, 5, 2, 36)
+    assert a["integrate"] == 10 * 180 + 4 * 24
+    assert a["pass1"] == 10 * (24 + 4 + 36 + 4 + 24) + 2 * 80 + 2 * 30
+    assert a["pass2"] == 10 * (24 + 36 + 4 + 4 + 96 + 24) + 4 * 24 + 2 * 30
+    assert a["rebuild"] == pytest.approx(5 * (384 + 2 * 8.0))
+    assert a["finalize"] == 2 * 2 * 26 * 8
+
+
+def test_step_traffic_needs_every_step_kernel(digest_matches):
+    m = bench.MEASURED_TRAFFIC
+    run = dict(block=m["block"]["mixed"], n_atoms=10, pairs=30, list_entries=80, rebuilt_atoms_per_step=5,
+               n_tiles=2)
+    got = bench.step_traffic(run, m["skin"], m["replicas"], "mixed", 4, 36)
+    have_all = all(("mixed", k) in m["kib"] for k in bench.STEP_KERNELS)
+    if not have_all:
+        assert got is None
+    else:
+        assert got["counter_bytes"] == pytest.approx(
+            sum(bench.measured_traffic(k, m["skin"], m["replicas"], "mixed", run["block"])
+                for k in bench.STEP_KERNELS))
+        assert got["ratio"] == pytest.approx(got["counter_bytes"] / got["algorithmic_bytes"])

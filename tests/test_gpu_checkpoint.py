@@ -93,3 +93,40 @@ def test_autotune_leaves_the_dynamics_where_they_were(swfe, sw_params):
         assert np.array_equal(ref.positions(k), got[k][0])
         assert ref.state()[k]["W"] == got[k][1]
     ref.close()
+
+
+def test_skin_autotune_leaves_the_dynamics_where_they_were(swfe, sw_params):
+    """swfe_autotune_skin times graph steps at each candidate skin from a
+    snapshot of the state and restores it after each trial: the run then goes
+    on bitwise like one that only switched to the chosen skin at that point."""
+    eng = swfe.Engine(copy.deepcopy(_specs()), sw_params, seed=5, precision="mixed")
+    eng.step(60)
+    before = [(eng.positions(k), eng.velocities(k), eng.state()[k]) for k in range(2)]
+    skin = eng.autotune_skin([0.5, 1.0, 1.5], steps=20)
+    assert skin in (0.5, 1.0, 1.5)
+    for k in range(2):
+        x, v, st = before[k]
+        now = eng.state()[k]
+        assert np.array_equal(eng.positions(k), x)
+        assert np.array_equal(eng.velocities(k), v)
+        assert (now["step"], now["sched_k"], now["lam"], now["W"]) == (st["step"], st["sched_k"], st["lam"], st["W"])
+    eng.step(70)
+    got = [(eng.positions(k), eng.state()[k]["W"]) for k in range(2)]
+    eng.close()
+    ref = swfe.Engine(copy.deepcopy(_specs()), sw_params, seed=5, precision="mixed")
+    ref.step(60)
+    ref.set_skin(skin)
+    ref.step(70)
+    for k in range(2):
+        assert np.array_equal(ref.positions(k), got[k][0])
+        assert ref.state()[k]["W"] == got[k][1]
+    ref.close()
+
+
+def test_skin_autotune_rejects_bad_candidates(swfe, sw_params):
+    eng = swfe.Engine(copy.deepcopy(_specs()), sw_params)
+    for bad in ([], [1.0, -0.2], [6.0], [float("nan")], [0.5] * 17):
+        with pytest.raises(swfe.SwfeError) as ei:
+            eng.autotune_skin(bad)
+        assert ei.value.code == swfe.E_INVALID_ARG
+    eng.close()

@@ -45,11 +45,15 @@ def test_switching_is_close_to_reversible(phases):
 def test_coexistence_pressure_at_400_K(phases):
     cd, bt = phases["cd"], phases["bt"]
     Pc = e2e.coexistence_pressure(phases)
-    sem = np.hypot(cd[:, 0].std(ddof=1), bt[:, 0].std(ddof=1)) / np.sqrt(e2e.CO_REAL)
-    dP = sem / ((cd[:, 1].mean() - bt[:, 1].mean()) * est.EV_A3_PER_GPA)
+    dP, dof = e2e.coexistence_pressure_se(phases)
     print(f"g(cd) - g(beta-tin) at {e2e.CO_P} GPa: {1e3 * (cd[:, 0].mean() - bt[:, 0].mean()):.3f} meV/atom; "
           f"P_coex(400 K) = {Pc:.3f} +- {dP:.3f} GPa (paper 13.17346(5))", flush=True)
-    assert abs(Pc - e2e.PAPER["coexistence_pressure_cd_beta_tin_400K"]["value"]) < 0.5
+    # P_coex(400 K) computed here sits 0.106 GPa below the paper's (twelve
+    # standard errors; recorded as an unexplained offset of this build): the
+    # check is this build's recorded value within three standard deviations'
+    # coverage of both measurements, and the offset kept below 0.12 GPa
+    assert abs(Pc - e2e.OWN_P_COEX_400K) < e2e.bound3([(dP, dof), (e2e.OWN_P_COEX_400K_SE, 6)])
+    assert abs(Pc - e2e.PAPER["coexistence_pressure_cd_beta_tin_400K"]["value"]) < 0.12
 
 
 def test_dcci_line_from_the_computed_point_reaches_the_triple_point(sw_params, phases):
@@ -59,10 +63,10 @@ def test_dcci_line_from_the_computed_point_reaches_the_triple_point(sw_params, p
     GPa).  An error d in the starting P_S stays in P_S and appears as
     d / lambda = d T / 400 K in the pressure, so the line from the paper's
     13.17346 GPa lies about 0.3 GPa higher at 1210 K."""
-    Pc = float(e2e.coexistence_pressure(phases))
+    Pc, (dPc, dof) = float(e2e.coexistence_pressure(phases)), e2e.coexistence_pressure_se(phases)
     curves = e2e.dcci_curves(sw_params, [("cd", "bt", 400.0, Pc, inputs.MODE_DCCI_T, 400.0, 1250.0)], seed0=500)
     Tt, Pt = e2e.TRIPLE
     ps = [np.interp(Tt, tp[:, 0], tp[:, 1]) for _, tp in curves.values()]
     print(f"cd/beta-tin from P_coex(400 K) = {Pc:.3f} GPa: P(1210 K) = {np.round(ps, 3)} GPa, "
           f"mean {np.mean(ps):.3f} (paper 9.90(3))", flush=True)
-    assert abs(np.mean(ps) - Pt) < 0.3
+    assert abs(np.mean(ps) - Pt) < e2e.three_sigma(ps, 0.03, (dPc * Tt / 400.0, dof))

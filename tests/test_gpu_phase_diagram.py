@@ -13,8 +13,11 @@ Phases: 4096-atom diamond, 8000-atom beta-tin, 8000-atom liquid; 30 ps of
 NPT equilibration at the starting point, Langevin 0.1 ps, barostat 1 ps,
 mixed precision, two independent realisations of every line, all twelve
 systems in one batch.  The paper's triple point is (1210(2) K, 9.90(3) GPa);
-the tolerances here allow for two realisations and for protocol details the
-paper does not give (equilibration length, barostat parameters).  Measured:
+the tolerances have the coverage of three standard deviations of the
+comparison: the paper's stated uncertainty combined with the standard error
+of the mean of the realisations here (Student t at the Welch-Satterthwaite
+degrees of freedom, which the paper's stated uncertainty dominates for the
+two realisations of a line).  Measured:
 the melting lines cross at (1210.3 K, 9.93 GPa); the cd/beta-tin line
 passes 1210 K at 10.12 +- 0.02 GPa (six realisations, insensitive to the
 equilibration length and barostat period), 0.2 GPa above the paper's
@@ -80,9 +83,17 @@ def _melting_crossing(curves):
 
 
 def test_cd_beta_tin_line_passes_the_triple_point(curves):
+    """From the paper's P_coex(400 K) the line passes 1210 K above the
+    triple point by the offset of the starting point: P_coex(400 K) computed
+    here is 0.106 GPa lower than the paper's (an offset this build does not
+    explain), and an error d in the starting P_S of a temperature-controlled
+    line reappears as d T / 400 K in the pressure, so the line from the
+    paper's point should pass 1210 K at 9.90 + 0.106 * 1210/400 = 10.22 GPa."""
     ps = _cd_beta_tin_at_1210(curves)
-    print(f"cd/beta-tin: P(1210 K) = {np.round(ps, 3)} GPa, mean {np.mean(ps):.3f} (paper 9.90(3))", flush=True)
-    assert abs(np.mean(ps) - P_TP) < 0.3
+    shift = (_P["coexistence_pressure_cd_beta_tin_400K"]["value"] - e2e.OWN_P_COEX_400K) * T_TP / 400.0
+    print(f"cd/beta-tin: P(1210 K) = {np.round(ps, 3)} GPa, mean {np.mean(ps):.3f} (paper 9.90(3); with the "
+          f"starting-point offset {P_TP + shift:.3f})", flush=True)
+    assert abs(np.mean(ps) - (P_TP + shift)) < e2e.three_sigma(ps, 0.03)
 
 
 @pytest.mark.parametrize("i", [1, 2])
@@ -93,7 +104,7 @@ def test_melting_lines_reach_the_triple_point(curves, i):
         ts.append(np.interp(P_TP, tp[o, 1], tp[o, 0]))
     name = "cd/liquid" if i == 1 else "beta-tin/liquid"
     print(f"{name}: T(9.90 GPa) = {np.round(ts, 1)} K, mean {np.mean(ts):.1f} (paper 1210(2))", flush=True)
-    assert abs(np.mean(ts) - T_TP) < 20.0
+    assert abs(np.mean(ts) - T_TP) < e2e.three_sigma(ts, 2.0)
 
 
 def test_melting_lines_cross_at_the_triple_point(curves):
@@ -101,7 +112,7 @@ def test_melting_lines_cross_at_the_triple_point(curves):
     of the paper's triple point."""
     Tt, Pt = _melting_crossing(curves)
     print(f"melting lines cross at ({Tt:.1f} K, {Pt:.3f} GPa); paper (1210(2) K, 9.90(3) GPa)", flush=True)
-    assert abs(Tt - T_TP) < 20.0 and abs(Pt - P_TP) < 0.3
+    assert abs(Tt - T_TP) < 3 * 2.0 and abs(Pt - P_TP) < 3 * 0.03
 
 
 def test_lines_from_the_computed_starting_points_meet_at_the_triple_point(sw_params):
@@ -111,7 +122,8 @@ def test_lines_from_the_computed_starting_points_meet_at_the_triple_point(sw_par
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    Pc = float(e2e.coexistence_pressure(e2e.cached("coexistence", e2e.coexistence_phases, sw_params)))
+    co = e2e.cached("coexistence", e2e.coexistence_phases, sw_params)
+    Pc, (dPc, dof) = float(e2e.coexistence_pressure(co)), e2e.coexistence_pressure_se(co)
     Tm = {c: float(e2e.melting_temperature(c, e2e.cached(("melting", c), e2e.melting_phases, sw_params, c)))
           for c in e2e.MELT_CASES}
     own = [("cd", "bt", 400.0, Pc, inputs.MODE_DCCI_T, 400.0, 1250.0),
@@ -120,11 +132,13 @@ def test_lines_from_the_computed_starting_points_meet_at_the_triple_point(sw_par
     curves = e2e.dcci_curves(sw_params, own, seed0=300)
     ps = _cd_beta_tin_at_1210(curves)
     Tt, Pt = _melting_crossing(curves)
+    print(f"cd/beta-tin at 1210 K by realisation: {np.round(ps, 3)} GPa", flush=True)
     print(f"from P_coex(400 K) = {Pc:.3f} GPa, T_m(0) = {Tm['cd_0GPa']:.1f} K, T_m(15 GPa) = "
           f"{Tm['bt_15GPa']:.1f} K: melting lines cross at ({Tt:.1f} K, {Pt:.3f} GPa), cd/beta-tin line at "
           f"{np.mean(ps):.3f} GPa at 1210 K; paper (1210(2) K, 9.90(3) GPa)", flush=True)
-    assert abs(Tt - T_TP) < 20.0 and abs(Pt - P_TP) < 0.3
-    assert abs(np.mean(ps) - P_TP) < 0.3
+    assert abs(Tt - T_TP) < 3 * 2.0 and abs(Pt - P_TP) < 3 * 0.03
+    # the line also carries its starting point's uncertainty, dPc T / 400 K
+    assert abs(np.mean(ps) - P_TP) < e2e.three_sigma(ps, 0.03, (dPc * T_TP / 400.0, dof))
 
 
 def test_dcci_converges_with_the_switching_time(sw_params):
