@@ -57,22 +57,28 @@ DF_STEPS = 1000
 DF_REALISATIONS = 32
 DF_ENSEMBLE_REPLICAS = {"diamond": 10, "beta-sn": 44, "liquid": 53}
 
-# HBM bytes per launch of the force passes and integrate on this workload (64 replicas,
+# HBM bytes per launch of the step kernels on this workload (64 replicas,
 # skin 1.4 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
-# averaged over the dispatches of a short run of both precisions), each
+# averaged over the dispatches of a short run of both precisions; a rebuild
+# stage's mean holds its steps with and without rebuilds), each
 # scaled by what the counter reads for a plain 512 MiB device copy:
 # FETCH_SIZE reads half the copied bytes (factor 2.000), WRITE_SIZE all of
 # them (1.000).  The figures hold only for the block sizes, the kernel
 # sources and the host code that places blocks on the XCDs they were taken
 # on (digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3b8592c28d00042e40b74b88e9e45fe25b4709ed567907280a360994f902566b",
+    "sources_sha256": "ff6bf0a34c6f288846b1c4f146e4b3332c752857fa82d0da2e9be60bdf152bed",
     "skin": 1.4, "replicas": 64, "block": {"mixed": 128, "fp64": 256},
     "fetch_factor": 2.0, "write_factor": 1.0,
     "kib": {  # (FETCH_SIZE, WRITE_SIZE)
-        ("mixed", "pass1"): (17774.3, 25538.8), ("mixed", "pass2"): (28159.2, 18587.6),
-        ("fp64", "pass1"): (16166.7, 34012.5), ("fp64", "pass2"): (28312.5, 18166.5),
-        ("mixed", "integrate"): (18147.7, 18217.4),
+        ("mixed", "pass1"): (17293.7, 23300.5), ("mixed", "pass2"): (27862.0, 18713.5),
+        ("fp64", "pass1"): (15824.2, 31878.4), ("fp64", "pass2"): (28320.2, 18293.1),
+        ("mixed", "integrate"): (18128.1, 18219.6), ("fp64", "integrate"): (18118.7, 18180.7),
+        ("mixed", "rebuild_count"): (253.1, 335.8), ("mixed", "rebuild_scatter"): (732.2, 1452.7),
+        ("mixed", "rebuild_order"): (712.2, 1712.1),
+        # kernels of one workgroup size in both precisions: mean over both runs
+        ("mixed", "rebuild_scan"): (59.5, 17.0), ("mixed", "rebuild_list"): (1688.6, 1343.9),
+        ("mixed", "finalize"): (506.4, 32.0),
     },
 }
 
@@ -516,7 +522,9 @@ def main():
                    "replicas": mixed["n_rep"], "atoms": mixed["n_atoms"], "precision": "mixed",
                    "dt_ps": 0.001, "forward_steps": steps // 2, "backward_steps": steps // 2,
                    "block": mixed["block"], "skin_A": mixed["skin"],
-                   "list_rebuilds_per_step": mixed["rebuilds_per_step"]},
+                   "list_rebuilds_per_step": mixed["rebuilds_per_step"],
+                   "rebuilt_atoms_per_step": mixed["rebuilt_atoms_per_step"],
+                   "ordered_pairs_within_rc": mixed["pairs"], "verlet_list_entries": mixed["list_entries"]},
         "timing": {"value_from": f"median of {REPEATS} timed windows of {mixed['steps']} steps",
                    "windows_s": mixed["walls"], "median_window_gpu_events_s": mixed["gpu"]},
     }

@@ -299,9 +299,9 @@ int swfe_autotune_skin(swfe_ctx *ctx, const double *candidates, int32_t n_candid
  * durations of integrate, rebuild count (with the rebuild decision),
  * rebuild scan, rebuild scatter,
  * rebuild order, rebuild list, pass1, pass2 and finalize (ms, host array of
- * 9).  When every system's cell table fits in LDS the first four rebuild
- * stages run as one fused sort per system, whose time the count entry holds
- * (scan, scatter and order then read 0).  Synchronises.  The steps advance
+ * 9).  When every system has at most 2048 atoms and a cell table that fits
+ * in LDS the first four rebuild stages run as one fused sort per system,
+ * whose time the count entry holds (scan, scatter and order then read 0).  Synchronises.  The steps advance
  * the systems like swfe_step_switched. */
 #define SWFE_NUM_KERNELS 9
 int swfe_profile_steps(swfe_ctx *ctx, int64_t n_steps, double *ms, void *stream);

@@ -204,7 +204,9 @@ __device__ __forceinline__ double total_force(int mode, double lam, double fint,
 }
 
 // Deterministic block reduction of NV doubles per thread into out[0..NV).
-template <int NV>
+// Only the slots in MASK are summed (the others are zero in every thread of
+// the caller, and are written as zeros).
+template <int NV, uint32_t MASK = (NV >= 32 ? ~0u : (1u << NV) - 1u)>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], double *out)
 {
     __shared__ double red[4][NV];
@@ -212,6 +214,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double *out)
     const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
+        if (!((MASK >> k) & 1u)) continue;
         double a = v[k];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
@@ -220,11 +223,23 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double *out)
     __syncthreads();
     if ((int)threadIdx.x < NV) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+        if ((MASK >> threadIdx.x) & 1u)
+            for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
         out[threadIdx.x] = s;
     }
     __syncthreads();  // red may be written again by the block's next call
 }
+
+// Slots of the tile partials each force pass fills (block_reduce masks):
+// pass 1 the two-body energy, the virial's upper triangle and the
+// three-body energy, with parameter gradients also the derivatives; pass 2
+// the virial's upper triangle, Einstein energy, kinetic energy and noise
+// sums, with gradients also its three parameter derivatives.
+constexpr uint32_t kVirUpper = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 5) | (1u << 6) | (1u << 9);
+constexpr uint32_t kPass1Slots = 1u | kVirUpper | (1u << P_E3);
+constexpr uint32_t kPass1GradSlots = kPass1Slots | (0x1FFu << P_DTH);
+constexpr uint32_t kPass2Slots = kVirUpper | (0x7Fu << P_UREF);
+constexpr uint32_t kPass2GradSlots = kPass2Slots | (1u << 14) | (1u << 16) | (1u << 17);
 
 __device__ __forceinline__ double block_max(double v)
 {
@@ -1090,9 +1105,9 @@ __device__ __forceinline__ void pass1_tile(const Ctl &c, const DevPtrs &p, const
         if (nin > kMaxShort) atomicOr(&p.state[sys].err, ERR_OVERFLOW);
         p.nnb[t] = nkeep;
         p.fs[t] = make_dvec3(F2x, F2y, F2z);
-        p.e_s[t] = acc[0] + acc[19];
+        if (!c.in_step) p.e_s[t] = acc[0] + acc[19];  // per-atom energies: force calls only
     }
-    block_reduce<NV>(acc, p.part1 + (int64_t)ti * kNumPart);
+    block_reduce<NV, GRAD ? kPass1GradSlots : kPass1Slots>(acc, p.part1 + (int64_t)ti * kNumPart);
 }
 
 template <typename R, bool GRAD>
@@ -1612,7 +1627,7 @@ __device__ __forceinline__ void pass2_tile(const Ctl &c, const DevPtrs &p, const
         acc[P_K + 2] = d.mvv2e_m * (v.z * v.z);
         if (GRAD && o_step_on(d)) next_normals(c, d, st, t, atom, p.zs, acc);
     }
-    block_reduce<NV>(acc, p.part2 + (int64_t)ti * kNumPart);
+    block_reduce<NV, GRAD ? kPass2GradSlots : kPass2Slots>(acc, p.part2 + (int64_t)ti * kNumPart);
 }
 
 template <typename R, bool GRAD>
