@@ -45,6 +45,10 @@ C_ATOM2 = 50    # per atom in pass 2: own three-body energy, Einstein spring, fi
 # their anchor (24).
 INTEGRATE_BYTES = 180
 INTEGRATE_BYTES_FL = 24
+# Bytes per atom-step of a step done in one pass over the atoms: position,
+# velocity and force each read and written once (3 x 48) and the cell
+# binning (12); Frenkel-Ladd atoms also read their anchor (24).
+ONE_PASS_BYTES = 156
 PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
 PEAK_HBM = 8.0e12                             # B/s
 SKINS = (0.4, 0.7, 1.0, 1.4, 1.8)  # Verlet skins the autotuner tries with --skin 0, A
@@ -150,7 +154,9 @@ def step_traffic(run, skin, replicas, precision, n_fl, mom_bytes):
                                  run["rebuilt_atoms_per_step"], run["n_tiles"], mom_bytes)
     counter = sum(meas.values())
     total = sum(alg.values())
+    one_pass = ONE_PASS_BYTES * run["n_atoms"] + INTEGRATE_BYTES_FL * n_fl
     return {"counter_bytes": counter, "algorithmic_bytes": total, "ratio": counter / total,
+            "one_pass_bytes": one_pass, "ratio_one_pass": counter / one_pass,
             "counter_bytes_per_kernel": meas, "algorithmic_bytes_per_kernel": alg}
 
 

@@ -103,3 +103,13 @@ def test_step_traffic_needs_every_step_kernel(digest_matches):
             sum(bench.measured_traffic(k, m["skin"], m["replicas"], "mixed", run["block"])
                 for k in bench.STEP_KERNELS))
         assert got["ratio"] == pytest.approx(got["counter_bytes"] / got["algorithmic_bytes"])
+
+
+def test_step_traffic_against_the_one_pass_budget(digest_matches):
+    m = bench.MEASURED_TRAFFIC
+    run = dict(block=m["block"]["mixed"], n_atoms=10, pairs=30, list_entries=80, rebuilt_atoms_per_step=5,
+               n_tiles=2)
+    got = bench.step_traffic(run, m["skin"], m["replicas"], "mixed", 4, 36)
+    if got is not None:
+        assert got["one_pass_bytes"] == 10 * 156 + 4 * 24
+        assert got["ratio_one_pass"] == pytest.approx(got["counter_bytes"] / got["one_pass_bytes"])

@@ -185,10 +185,15 @@ def test_dense_neighbourhoods_past_the_on_chip_short_list(swfe, sw_params, prec,
     _, most, _ = eng.neighbor_stats()
     ref = orc.sw_eval(s.x, s.box, sw_params)
     assert most > 24
-    # the net forces are small against the cancelling pair and triplet
-    # contributions (~45 eV/atom of repulsion), which sets the mixed bar
+    F = eng.forces(0)
+    # A stress case, not one of the workload's phases (those hold the mixed
+    # bar of 1e-5 relative, every replica of the 64-replica batch included):
+    # the net forces (at most 5.9 eV/A here) are what is left of pair and
+    # triplet parts of up to 6.8 eV/A each, summed from ~40 neighbours whose
+    # FP32 terms are each rounded at their own, larger magnitude.
     tol_f, tol_e = (1e-10, 1e-12) if prec == "fp64" else (1e-4, 1e-6)
-    assert force_err(eng.forces(0), ref["F"]) < tol_f
+    print(f"dense fcc {prec}: force err {force_err(F, ref['F']):.2e}", flush=True)
+    assert force_err(F, ref["F"]) < tol_f
     assert out[0] == pytest.approx(ref["E"], rel=tol_e)
     eng.close()
 
