@@ -264,12 +264,13 @@ int swfe_set_log(swfe_ctx *ctx, int32_t log_every, int32_t capacity);
 int swfe_read_log(swfe_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows, void *stream);
 
 /* Tuning: block size of the per-atom kernels (64, 128 or 256; 0 = autotune).
- * swfe_autotune times a few dynamics steps at each size from the current
- * state (the faster of two interleaved rounds), restoring the state after
- * each through a host snapshot (swfe_save_state / swfe_load_state; it
- * allocates swfe_checkpoint_bytes of host memory for the call), and keeps
- * the largest size within 1 % of the fastest.  It recomputes forces at the
- * chosen size but does not advance the dynamics. */
+ * swfe_autotune times 24 graph-replayed dynamics steps (after 3 untimed
+ * ones) at each size from the current state (the fastest of three
+ * interleaved rounds), restoring the state after each through a host
+ * snapshot (swfe_save_state / swfe_load_state; it allocates
+ * swfe_checkpoint_bytes of host memory for the call), and keeps the fastest
+ * size.  It recomputes forces at the chosen size but does not advance the
+ * dynamics. */
 int swfe_set_block(swfe_ctx *ctx, int32_t block, void *stream);
 int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream);
 

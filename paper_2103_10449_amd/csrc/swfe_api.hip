@@ -472,6 +472,9 @@ Ctl make_ctl_raw(const SysDesc *desc, int n_sys, int n_tiles, int n_groups, int6
         max_atoms = std::max(max_atoms, desc[i].n);
     }
     k.sort_cells = max_cells <= kSortLdsCells && max_atoms <= kSortFuseMaxAtoms ? max_cells : 0;
+    // otherwise the scatter stage scans the cell counts of a rebuilding
+    // system in LDS when every system's table fits (one launch fewer)
+    k.scan_cells = k.sort_cells == 0 && max_cells <= kSortLdsCells ? max_cells : 0;
     k.in_step = in_step;
     k.force_rebuild = force_rebuild;
     k.log_every = log_every;
@@ -1086,10 +1089,10 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
 {
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     hipStream_t s = (hipStream_t)stream;
-    // Every candidate runs a few eager dynamics steps from the current state
-    // (the block size changes the cost of every per-atom kernel, not only of
-    // the force passes), and a host snapshot of the state is restored after
-    // each, so the call leaves the dynamics where they were.
+    // Every candidate runs graph-replayed dynamics steps from the current
+    // state, as a run does (the block size changes the cost of every per-atom
+    // kernel, not only of the force passes), and a host snapshot of the state
+    // is restored after each, so the call leaves the dynamics where they were.
     size_t bytes = 0;
     RCHK(swfe_checkpoint_bytes(ctx, &bytes));
     std::vector<char> snap(bytes);
@@ -1097,15 +1100,14 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
-    constexpr int kSteps = 8;
+    constexpr int kSteps = 24;
     const int cand[3] = {64, 128, 256};
     float best_ms[3] = {1e30f, 1e30f, 1e30f};
     auto trial = [&](int q) -> int {
         RCHK(swfe_set_block(ctx, cand[q], stream));
-        Ctl k = make_ctl(ctx, 1, 0, 0);
-        HIPCHK(ctx, launch_begin_step(k, ctx->ptrs, ctx->sw, kSteps, s));
+        RCHK(swfe_step_switched(ctx, 3, 1, stream));  // capture and warm the step graph
         HIPCHK(ctx, hipEventRecord(e0, s));
-        for (int i = 0; i < kSteps; ++i) RCHK(enqueue_step(ctx, s));
+        RCHK(swfe_step_switched(ctx, kSteps, 1, stream));
         HIPCHK(ctx, hipEventRecord(e1, s));
         HIPCHK(ctx, hipEventSynchronize(e1));
         float ms = 0;
@@ -1113,18 +1115,20 @@ int swfe_autotune(swfe_ctx *ctx, int32_t *chosen_block, void *stream)
         best_ms[q] = std::min(best_ms[q], ms);
         return swfe_load_state(ctx, snap.data(), bytes, stream);
     };
-    // two interleaved rounds, the faster of each candidate's counting
+    // three interleaved rounds, the fastest of each candidate's counting
     int rc = SWFE_OK;
-    for (int round = 0; round < 2 && rc == SWFE_OK; ++round)
+    for (int round = 0; round < 3 && rc == SWFE_OK; ++round)
         for (int q = 0; q < 3 && rc == SWFE_OK; ++q) rc = trial(q);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    // the largest block within 1 % of the fastest
-    const float fastest = std::min(best_ms[0], std::min(best_ms[1], best_ms[2]));
     int best_b = cand[0];
-    for (int q = 0; q < 3; ++q)
-        if (best_ms[q] <= 1.01f * fastest) best_b = cand[q];
+    float fastest = best_ms[0];
+    for (int q = 1; q < 3; ++q)
+        if (best_ms[q] < fastest) {
+            fastest = best_ms[q];
+            best_b = cand[q];
+        }
     if (chosen_block) *chosen_block = best_b;
     return swfe_set_block(ctx, best_b, stream);
 }

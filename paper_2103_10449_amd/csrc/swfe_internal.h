@@ -149,7 +149,8 @@ struct Ctl {
     int32_t force_rebuild;  // 1: rebuild every system's list now
     int32_t log_every, log_cap;
     int32_t sort_cells;     // LDS cell-table entries of the fused sort (0: separate stages)
-    int32_t pad_;
+    int32_t scan_cells;     // > 0: the scatter stage scans each system's cell counts in LDS (this many
+                            // entries) and the scan launch is skipped; 0: separate scan launch
     // The tiles are cut into 8 * kFxChunks runs of fx_len tiles; XCD x runs
     // the runs fx_chunk[x * kFxChunks + j], j < kFxChunks.
     int32_t fx_chunk[8 * kFxChunks];

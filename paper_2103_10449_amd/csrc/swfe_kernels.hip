@@ -437,7 +437,10 @@ __device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, i
     if (c.force_rebuild) return true;
     const SysDesc &d = p.desc[sys];
     const SysState &st = p.state[sys];
-    const double m = p.disp_max[2 * sys + (st.step & 1)];
+    // both displacement slots load with the state (no wait for the step
+    // count before the slot's load)
+    const double m0 = p.disp_max[2 * sys], m1 = p.disp_max[2 * sys + 1];
+    const double m = (st.step & 1) ? m1 : m0;
     double smin = 1e300;
     for (int k = 0; k < 3; ++k) smin = fmin(smin, (st.box[k] * st.pscale[k]) / st.box_build[k]);
     const double shrink = smin < 1.0 ? 1.0 - smin : 0.0;
@@ -446,7 +449,8 @@ __device__ bool list_stale(const Ctl &c, const DevPtrs &p, const SwParams &sw, i
 
 // Binning of the atoms of every system whose list is stale (each block
 // takes the decision for its tile's system; the scan stage takes the same
-// decision from the same inputs).  The rebuild work list starts empty.
+// decision from the same inputs).  The rebuild work list starts empty
+// (integrate or gather empties it).
 __device__ __forceinline__ void rb_count_tile(const DevPtrs &p, const SwParams &sw, int ti)
 {
     const Tile tile = p.tiles[ti];
@@ -456,13 +460,38 @@ __device__ __forceinline__ void rb_count_tile(const DevPtrs &p, const SwParams &
     }
 }
 
+// The displacement slots of one system at a rebuild decision: the slot the
+// next step's integrate fills is cleared (both on a forced build, which
+// reads neither).
+__device__ __forceinline__ void clear_disp_slots(const Ctl &c, const DevPtrs &p, int sys)
+{
+    const int64_t step = p.state[sys].step;
+    p.disp_max[2 * sys + ((step + 1) & 1)] = 0.0;
+    if (c.force_rebuild) p.disp_max[2 * sys + (step & 1)] = 0.0;
+}
+
 __global__ void __launch_bounds__(256) k_rb_count(Ctl c, DevPtrs p, SwParams sw)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.n_work[0] = 0;
     const int ti = tile_of_block(c);
     if (ti < 0) return;
-    if (!list_stale(c, p, sw, p.tiles[ti].sys)) return;
-    rb_count_tile(p, sw, ti);
+    const Tile tile = p.tiles[ti];
+    const int sys = tile.sys;
+    // the block's positions load with the rebuild decision's inputs
+    const int a = (int)threadIdx.x < tile.count ? (int)threadIdx.x : 0;
+    const double4 x = p.xs[tile.start + a];
+    // without a scan launch, the block of a system's first tile clears its
+    // displacement slot (a slot the decision below does not read)
+    if (c.scan_cells > 0 && threadIdx.x == 0 && ti == p.desc[sys].tile_begin) clear_disp_slots(c, p, sys);
+    if (!list_stale(c, p, sw, sys)) return;
+    if (tile.count <= (int)blockDim.x) {
+        if ((int)threadIdx.x < tile.count)
+            bin_atom(p, sw, p.desc[sys], p.state[sys], tile.start + a, x);
+    } else {
+        rb_count_tile(p, sw, ti);
+    }
+    // and each stale tile goes to the work list of the later stages itself
+    // (their tiles are independent: the order of the list does not matter)
+    if (c.scan_cells > 0 && threadIdx.x == 0) p.work[atomicAdd(&p.n_work[0], 1)] = ti;
 }
 
 // For one system, by all threads of a block: clear the next step's
@@ -485,9 +514,7 @@ __device__ void rb_scan_sys(const Ctl &c, const DevPtrs &p, const SwParams &sw, 
     const int tid = threadIdx.x, nth = blockDim.x;
     __shared__ int at_s;
     if (tid == 0) {
-        // clear the slot the next step's integrate fills (both on a forced build)
-        p.disp_max[2 * sys + ((st.step + 1) & 1)] = 0.0;
-        if (c.force_rebuild) p.disp_max[2 * sys + (st.step & 1)] = 0.0;
+        clear_disp_slots(c, p, sys);
         at_s = rb && append ? atomicAdd(&p.n_work[0], d.tile_end - d.tile_begin) : 0;
     }
     __syncthreads();
@@ -537,7 +564,8 @@ __global__ void __launch_bounds__(kSortThreads) k_rb_scan(Ctl c, DevPtrs p, SwPa
 
 // Atom data into its cell's segment of the staging arrays (slot by rank, so
 // the order inside a cell is not yet fixed).
-__device__ __forceinline__ void rb_scatter_tile(const DevPtrs &p, int ti)
+// lstart: the system's cell starts in LDS, or null to read them from memory
+__device__ __forceinline__ void rb_scatter_tile(const DevPtrs &p, int ti, const int32_t *lstart)
 {
     const Tile tile = p.tiles[ti];
     for (int a = threadIdx.x; a < tile.count; a += blockDim.x) {
@@ -545,7 +573,7 @@ __device__ __forceinline__ void rb_scatter_tile(const DevPtrs &p, int ti)
         const SysDesc &d = p.desc[sys];
         const int t = tile.start + a;
         const int cell = p.cellid[t];
-        const int s = p.cell_start[d.cell_base + sys + cell] + p.rank[t];
+        const int s = (lstart ? lstart[cell] : p.cell_start[d.cell_base + sys + cell]) + p.rank[t];
         p.txs[s] = p.xs[t];
         p.tvs[s] = p.vs[t];
         p.tfs[s] = p.fs[t];
@@ -555,10 +583,73 @@ __device__ __forceinline__ void rb_scatter_tile(const DevPtrs &p, int ti)
     }
 }
 
-__global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p)
+// Exclusive scan of a rebuilding system's cell counts into LDS (nc + 1
+// entries: cell starts in sorted positions, then the system's end), by all
+// threads of the block (at most 256).  The block of the system's first tile
+// also writes them out for the later stages, with the build box and the
+// rebuild count.  Same arithmetic as the scan stage.
+__device__ void scan_cells_lds(const Ctl &c, const DevPtrs &p, const SwParams &sw, int sys, bool first,
+                               int32_t *lstart)
 {
+    SysState &st = p.state[sys];
+    const SysDesc &d = p.desc[sys];
+    double box[3], ibox[3];
+    int nc3[3];
+    eff_box(st, box, ibox);
+    cell_grid(d, box, list_radius(sw, d), nc3);
+    const int nc = nc3[0] * nc3[1] * nc3[2];
+    const int32_t *cnt = p.cell_count + d.cell_base;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ int32_t wsum[4];
+    for (int q = tid; q < nc; q += nth) lstart[q] = cnt[q];
+    __syncthreads();
+    const int per = (nc + nth - 1) / nth;
+    const int lo = min(tid * per, nc), hi = min(lo + per, nc);
+    int sum = 0;
+    for (int q = lo; q < hi; ++q) sum += lstart[q];
+    // inclusive scan of the segment sums: within each wave by lane
+    // exchanges, then over the waves' totals
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) incl += wsum[w];
+    int run = (int)d.off + incl - sum;
+    for (int q = lo; q < hi; ++q) {
+        const int k = lstart[q];
+        lstart[q] = run;
+        run += k;
+    }
+    if (tid == 0) lstart[nc] = (int)(d.off + d.n);
+    __syncthreads();
+    if (first) {
+        int32_t *start = p.cell_start + d.cell_base + sys;
+        for (int q = tid; q <= nc; q += nth) start[q] = lstart[q];
+        if (tid == 0) {
+            for (int k = 0; k < 3; ++k) st.box_build[k] = box[k];
+            st.n_rebuild += 1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rb_scatter(Ctl c, DevPtrs p, SwParams sw)
+{
+    extern __shared__ int32_t lstart[];  // c.scan_cells entries when the scan is folded in
     const int n_work = p.n_work[0];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) rb_scatter_tile(p, p.work[w]);
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const int ti = p.work[w];
+        if (c.scan_cells > 0) {
+            const int sys = p.tiles[ti].sys;
+            scan_cells_lds(c, p, sw, sys, ti == p.desc[sys].tile_begin, lstart);
+            rb_scatter_tile(p, ti, lstart);
+            __syncthreads();  // lstart is written again for the block's next tile
+        } else {
+            rb_scatter_tile(p, ti, nullptr);
+        }
+    }
 }
 
 // Final order: inside a cell atoms follow the caller's atom index.  Each
@@ -590,10 +681,27 @@ __device__ __forceinline__ void rb_order_tile(const DevPtrs &p, int ti)
     }
 }
 
-__global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p)
+__global__ void __launch_bounds__(256) k_rb_order(Ctl c, DevPtrs p, SwParams sw)
 {
     const int n_work = p.n_work[0];
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) rb_order_tile(p, p.work[w]);
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const int ti = p.work[w];
+        rb_order_tile(p, ti);
+        if (c.scan_cells > 0) {
+            // the counts were last read by the scatter stage: clear them for
+            // the next binning (the block of the system's first tile)
+            const int sys = p.tiles[ti].sys;
+            const SysDesc &d = p.desc[sys];
+            if (ti == d.tile_begin) {
+                double box[3], ibox[3];
+                int nc3[3];
+                eff_box(p.state[sys], box, ibox);
+                cell_grid(d, box, list_radius(sw, d), nc3);
+                const int nc = nc3[0] * nc3[1] * nc3[2];
+                for (int q = threadIdx.x; q < nc; q += blockDim.x) p.cell_count[d.cell_base + q] = 0;
+            }
+        }
+    }
 }
 
 // Rebuild stages 0-3 fused, one workgroup of kSortThreads per system (used
@@ -1859,7 +1967,7 @@ k_persist(Ctl c, DevPtrs p, SwParams sw, XcdPlan xp, int64_t n_steps)
                 if (s_stale[q - sb]) rb_scan_sys<256>(c, p, sw, p.xsys[q], true, false);
             SWFE_XCD_SYNC();
             for (int i = tb + j; i < te; i += nb)
-                if (s_stale[p.xtloc[i]]) rb_scatter_tile(p, p.xtiles[i]);
+                if (s_stale[p.xtloc[i]]) rb_scatter_tile(p, p.xtiles[i], nullptr);
             SWFE_XCD_SYNC();
             for (int i = tb + j; i < te; i += nb)
                 if (s_stale[p.xtloc[i]]) rb_order_tile(p, p.xtiles[i]);
@@ -1944,9 +2052,16 @@ hipError_t launch_rebuild(const Ctl &c, const DevPtrs &p, const SwParams &sw, in
     }
     switch (stage) {
         case 0: hipLaunchKernelGGL(k_rb_count, tile_grid(c), dim3(block), 0, s, c, p, sw); break;
-        case 1: hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw); break;
-        case 2: hipLaunchKernelGGL(k_rb_scatter, dim3(kWorkGrid), dim3(block), 0, s, c, p); break;
-        case 3: hipLaunchKernelGGL(k_rb_order, dim3(kWorkGrid), dim3(block), 0, s, c, p); break;
+        case 1:
+            // folded into the scatter stage when the cell tables fit in LDS
+            if (c.scan_cells == 0)
+                hipLaunchKernelGGL(k_rb_scan, dim3(c.n_sys), dim3(kSortThreads), 0, s, c, p, sw);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_rb_scatter, dim3(kWorkGrid), dim3(block), sizeof(int32_t) * (size_t)c.scan_cells,
+                               s, c, p, sw);
+            break;
+        case 3: hipLaunchKernelGGL(k_rb_order, dim3(kWorkGrid), dim3(block), 0, s, c, p, sw); break;
         default:
             hipLaunchKernelGGL(k_rb_list, dim3(4 * kWorkGrid), dim3(256), 0, s, c, p, sw, (block + 7) / 8);
             break;
