@@ -474,21 +474,12 @@ __global__ void __launch_bounds__(256) k_rb_count(Ctl c, DevPtrs p, SwParams sw)
 {
     const int ti = tile_of_block(c);
     if (ti < 0) return;
-    const Tile tile = p.tiles[ti];
-    const int sys = tile.sys;
-    // the block's positions load with the rebuild decision's inputs
-    const int a = (int)threadIdx.x < tile.count ? (int)threadIdx.x : 0;
-    const double4 x = p.xs[tile.start + a];
+    const int sys = p.tiles[ti].sys;
     // without a scan launch, the block of a system's first tile clears its
     // displacement slot (a slot the decision below does not read)
     if (c.scan_cells > 0 && threadIdx.x == 0 && ti == p.desc[sys].tile_begin) clear_disp_slots(c, p, sys);
     if (!list_stale(c, p, sw, sys)) return;
-    if (tile.count <= (int)blockDim.x) {
-        if ((int)threadIdx.x < tile.count)
-            bin_atom(p, sw, p.desc[sys], p.state[sys], tile.start + a, x);
-    } else {
-        rb_count_tile(p, sw, ti);
-    }
+    rb_count_tile(p, sw, ti);
     // and each stale tile goes to the work list of the later stages itself
     // (their tiles are independent: the order of the list does not matter)
     if (c.scan_cells > 0 && threadIdx.x == 0) p.work[atomicAdd(&p.n_work[0], 1)] = ti;
