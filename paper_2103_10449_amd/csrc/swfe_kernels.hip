@@ -1475,6 +1475,61 @@ __device__ __forceinline__ void block_copy(void *dst, const void *src, int n)
         static_cast<int32_t *>(dst)[w] = static_cast<const int32_t *>(src)[w];
 }
 
+// The sums of one system into its state, the outputs of a force call, and
+// at the end of a dynamics step the closing barostat half step (step 9),
+// the counters and the log row.  Returns the steps left in the call (0
+// outside a step).
+__device__ __forceinline__ int64_t finish_system(const Ctl &c, const DevPtrs &p, const SysDesc &d, SysState &st,
+                                                 const double *a, const double *b, int s, bool step_end)
+{
+    int64_t remaining = 0;
+    st.E2 = a[P_E];
+    st.E3 = a[P_E3];
+    st.U_int = st.E2 + st.E3;
+    for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
+    st.vir[3] = st.vir[1];  // lower triangle from the upper one
+    st.vir[6] = st.vir[2];
+    st.vir[7] = st.vir[5];
+    for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
+    st.U_ref = b[P_UREF] + (d.mode == MODE_UF ? a[P_UUF] : 0.0);
+    for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
+    st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
+    for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
+    st.V = st.box[0] * st.box[1] * st.box[2];
+    if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
+        st.err |= ERR_NONFINITE;
+    if (p.out) {
+        // dE/dstrain at diagonal strain e: Xi' (I + e)^-T
+        const double gsc = p.grad_scale ? p.grad_scale[s] : 1.0;
+        double *o = p.out + (int64_t)s * 20;
+        o[0] = st.U_int;
+        o[1] = st.U_ref;
+        for (int u = 0; u < 3; ++u)
+            for (int w = 0; w < 3; ++w) o[2 + 3 * u + w] = st.vir[3 * u + w] / st.pscale[w] * gsc;
+        for (int m = 0; m < 9; ++m) o[11 + m] = st.dth[m] * gsc;
+    }
+    if (step_end) {
+        baro_half(d, st, c.dt);  // step 9
+        st.step += 1;
+        st.k += 1;
+        st.remaining -= 1;
+        remaining = st.remaining;
+        if (c.log_every > 0 && c.log_cap > 0 && (st.step % c.log_every) == 0) {
+            const int64_t row = ((st.step / c.log_every) * c.n_sys + s) % c.log_cap;
+            double *L = p.log + row * 8;
+            L[0] = (double)st.step;
+            L[1] = st.lam;
+            L[2] = st.Ps * kGpaPerEvA3;
+            L[3] = st.lam != 0.0 ? st.Ps / st.lam * kGpaPerEvA3 : 0.0;
+            L[4] = 2.0 * st.K / (d.nf * 8.617333262e-5);
+            L[5] = st.U_int / (double)d.n;
+            L[6] = st.V / (double)d.n;
+            L[7] = st.W;
+        }
+    }
+    return remaining;
+}
+
 // Reductions of one group over its tiles in a fixed order (all threads of
 // the block), then the scalar update by thread 0 on copies of the group's
 // descriptors and states held in LDS (one load and one store of each field
@@ -1525,59 +1580,19 @@ __device__ void group_finalize(const Ctl &c, const DevPtrs &p, const SwParams &s
     }
     if (threadIdx.x == 0) {
         const bool step_end = c.in_step != 0;
-        int64_t remaining = 0;
-        for (int q = 0; q < nq; ++q) {
-            const int s = sid[q];
-            const SysDesc &d = sdesc[q];
-            SysState &st = sst[q];
-            const double *a = sums[q], *b = sums[q] + kNumPart;
-            st.E2 = a[P_E];
-            st.E3 = a[P_E3];
-            st.U_int = st.E2 + st.E3;
-            for (int m = 0; m < 9; ++m) st.vir[m] = a[P_VIR + m] + b[P_VIR + m];
-            st.vir[3] = st.vir[1];  // lower triangle from the upper one
-            st.vir[6] = st.vir[2];
-            st.vir[7] = st.vir[5];
-            for (int m = 0; m < 9; ++m) st.dth[m] = a[P_DTH + m] + b[P_DTH + m];
-            st.U_ref = b[P_UREF] + (d.mode == MODE_UF ? a[P_UUF] : 0.0);
-            for (int m = 0; m < 3; ++m) st.K3[m] = b[P_K + m];
-            st.K = (st.K3[0] + st.K3[1]) + st.K3[2];
-            for (int m = 0; m < 3; ++m) st.noise_mean[m] = b[P_NOISE + m] / (double)d.n;
-            st.V = st.box[0] * st.box[1] * st.box[2];
-            if (!isfinite(st.U_int) || !isfinite(st.K) || !isfinite(st.vir[0] + st.vir[4] + st.vir[8]))
-                st.err |= ERR_NONFINITE;
-            if (p.out) {
-                // dE/dstrain at diagonal strain e: Xi' (I + e)^-T
-                const double gsc = p.grad_scale ? p.grad_scale[s] : 1.0;
-                double *o = p.out + (int64_t)s * 20;
-                o[0] = st.U_int;
-                o[1] = st.U_ref;
-                for (int u = 0; u < 3; ++u)
-                    for (int w = 0; w < 3; ++w) o[2 + 3 * u + w] = st.vir[3 * u + w] / st.pscale[w] * gsc;
-                for (int m = 0; m < 9; ++m) o[11 + m] = st.dth[m] * gsc;
-            }
-            if (step_end) {
-                baro_half(d, st, c.dt);  // step 9
-                st.step += 1;
-                st.k += 1;
-                st.remaining -= 1;
-                remaining = st.remaining;
-                if (c.log_every > 0 && c.log_cap > 0 && (st.step % c.log_every) == 0) {
-                    const int64_t row = ((st.step / c.log_every) * c.n_sys + s) % c.log_cap;
-                    double *L = p.log + row * 8;
-                    L[0] = (double)st.step;
-                    L[1] = st.lam;
-                    L[2] = st.Ps * kGpaPerEvA3;
-                    L[3] = st.lam != 0.0 ? st.Ps / st.lam * kGpaPerEvA3 : 0.0;
-                    L[4] = 2.0 * st.K / (d.nf * 8.617333262e-5);
-                    L[5] = st.U_int / (double)d.n;
-                    L[6] = st.V / (double)d.n;
-                    L[7] = st.W;
-                }
-            }
+        if (nq == 1) {
+            // one system: the scalar chain runs on a register copy of its
+            // state (no LDS round trip per field)
+            SysState st = sst[0];
+            const int64_t remaining = finish_system(c, p, sdesc[0], st, sums[0], sums[0] + kNumPart, sid[0], step_end);
+            if (step_end && remaining > 0) group_start_step(c, sw, sdesc[0], st, nullptr, nullptr);
+            sst[0] = st;
+        } else {
+            int64_t remaining = 0;
+            for (int q = 0; q < 2; ++q)
+                remaining = finish_system(c, p, sdesc[q], sst[q], sums[q], sums[q] + kNumPart, sid[q], step_end);
+            if (step_end && remaining > 0) group_start_step(c, sw, sdesc[0], sst[0], &sdesc[1], &sst[1]);
         }
-        if (step_end && remaining > 0)
-            group_start_step(c, sw, sdesc[0], sst[0], nq == 2 ? &sdesc[1] : nullptr, nq == 2 ? &sst[1] : nullptr);
     }
     __syncthreads();
     for (int q = 0; q < nq; ++q) block_copy(&p.state[sid[q]], &sst[q], sizeof(SysState));
