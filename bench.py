@@ -71,19 +71,19 @@ DF_ENSEMBLE_REPLICAS = {"diamond": 10, "beta-sn": 44, "liquid": 53}
 # sources and the host code that places blocks on the XCDs they were taken
 # on (digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "5a7ac391b994a9b9145b825544c68f5aecae3167c0526beeedb7e093bc73da7b",
+    "sources_sha256": "a34761dbf10f9bb2ac6e579eba4a5d5780fdb93a296bed1cb44ae1201658197a",
     "skin": 1.4, "replicas": 64, "block": {"mixed": 128, "fp64": 256},
     "fetch_factor": 2.0, "write_factor": 1.0,
     "kib": {  # (FETCH_SIZE, WRITE_SIZE)
-        ("mixed", "pass1"): (17287.2, 23306.0), ("mixed", "pass2"): (27879.9, 18716.0),
-        ("fp64", "pass1"): (15821.2, 31879.0), ("fp64", "pass2"): (28324.0, 18293.1),
-        ("mixed", "integrate"): (18127.9, 18220.5), ("fp64", "integrate"): (18118.9, 18180.2),
-        ("mixed", "rebuild_count"): (264.9, 340.8), ("mixed", "rebuild_scatter"): (762.4, 1450.7),
-        ("mixed", "rebuild_order"): (711.3, 1715.8),
+        ("mixed", "pass1"): (17350.7, 23293.2), ("mixed", "pass2"): (28060.8, 18696.8),
+        ("fp64", "pass1"): (15821.1, 31879.1), ("fp64", "pass2"): (28220.8, 18292.7),
+        ("mixed", "integrate"): (18130.8, 18219.8), ("fp64", "integrate"): (18119.9, 18179.3),
+        ("mixed", "rebuild_count"): (264.7, 340.9), ("mixed", "rebuild_scatter"): (762.3, 1450.6),
+        ("mixed", "rebuild_order"): (711.3, 1715.9),
         # the scan runs inside the scatter stage on this workload: no launch
         ("mixed", "rebuild_scan"): (0.0, 0.0),
         # kernels of one workgroup size in both precisions: mean over both runs
-        ("mixed", "rebuild_list"): (2028.7, 1346.4), ("mixed", "finalize"): (495.5, 32.0),
+        ("mixed", "rebuild_list"): (2026.1, 1346.4), ("mixed", "finalize"): (488.3, 32.0),
     },
 }
 

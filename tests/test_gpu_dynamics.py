@@ -214,3 +214,45 @@ def test_verlet_skin_does_not_change_results(swfe, sw_params, skin):
     assert abs(st["W"] - s.W) < 1e-9 * max(1.0, abs(s.W))
     assert st["n_rebuild"] >= (150 if skin == 0.0 else 2)
     eng.close()
+
+
+def _dilute_gas(seed):
+    """1 728 atoms on a perturbed simple-cubic lattice of 12.5 A spacing in a
+    150 A box: no pair within the cutoff, and a cell table (37^3 entries at a
+    0.2 A skin) larger than the cell scan keeps in LDS."""
+    g = np.arange(12) * 12.5 + 6.25
+    xl = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    x = inputs.perturb(xl, 0.5, inputs.rng(708, seed, 0))
+    v = inputs.maxwell(len(x), 1000.0, inputs.rng(708, seed, 1))
+    return inputs.SystemSpec(x=x, v=v, box=np.array([150.0, 150.0, 150.0]), phase="gas", mode=inputs.MODE_NVT,
+                             T0=1000.0, tau_damp=0.1, stream=50)
+
+
+def test_rebuild_paths_agree_bitwise(swfe, sw_params):
+    """The three ways a list rebuild re-sorts the atoms give the same atom
+    order, hence the same trajectory bit for bit: the 216-atom crystal alone
+    (every system small: one workgroup per system sorts in LDS), beside a
+    3 000-atom liquid (the cell scan runs inside the scatter stage), and
+    beside a dilute gas whose cell table is too large for LDS (a scan launch
+    of its own).  A 0.2 A skin makes the crystal rebuild its list often."""
+    crystal = lambda: diamond_spec(3, 91, mode=inputs.MODE_FL, k_spring=5.0, T0=1000.0, tau_damp=0.1, stream=7,
+                                   sched_start=1.0, sched_end=0.0, sched_steps=80)
+    others = {"sort in LDS": [],
+              "scan in the scatter stage": [liquid_spec(3000, 92, mode=inputs.MODE_NVT, T0=1700.0, tau_damp=0.1,
+                                                        stream=8)],
+              "scan launch": [_dilute_gas(93)]}
+    got = {}
+    for name, rest in others.items():
+        print(f"rebuild path: {name}", flush=True)
+        eng = swfe.Engine([crystal()] + rest, sw_params, seed=11, block=128)
+        eng.set_skin(0.2)
+        eng.step(80)
+        st = eng.state()
+        assert st[0]["n_rebuild"] > 5
+        got[name] = (eng.positions(0), eng.velocities(0), st[0]["W"])
+        eng.close()
+    ref = got["sort in LDS"]
+    for name, (x, v, W) in got.items():
+        assert np.array_equal(x, ref[0]), name
+        assert np.array_equal(v, ref[1]), name
+        assert W == ref[2], name
