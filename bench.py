@@ -51,7 +51,7 @@ INTEGRATE_BYTES_FL = 24
 ONE_PASS_BYTES = 156
 PEAK = {"mixed": 157.3e12, "fp64": 78.6e12}  # vector FLOP/s: FP32, FP64
 PEAK_HBM = 8.0e12                             # B/s
-SKINS = (0.4, 0.7, 1.0, 1.4, 1.8)  # Verlet skins the autotuner tries with --skin 0, A
+SKINS = (0.7, 1.0, 1.4, 1.8, 2.0)  # Verlet skins the autotuner tries with --skin 0, A
 REPEATS = 5                   # timed windows of K steps; the value is their median
 PEAK_FP32_NONPACKED = 78.6e12 # FP32 vector roof without packed FP32 instructions (the library's build)
 # Delta F gate: the switching protocol of the workload (1000 steps each way),
@@ -62,7 +62,7 @@ DF_REALISATIONS = 32
 DF_ENSEMBLE_REPLICAS = {"diamond": 10, "beta-sn": 44, "liquid": 53}
 
 # HBM bytes per launch of the step kernels on this workload (64 replicas,
-# skin 1.4 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+# skin 1.8 A), from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
 # averaged over the dispatches of a short run of both precisions; a rebuild
 # stage's mean holds its steps with and without rebuilds), each
 # scaled by what the counter reads for a plain 512 MiB device copy:
@@ -71,19 +71,19 @@ DF_ENSEMBLE_REPLICAS = {"diamond": 10, "beta-sn": 44, "liquid": 53}
 # sources and the host code that places blocks on the XCDs they were taken
 # on (digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a34761dbf10f9bb2ac6e579eba4a5d5780fdb93a296bed1cb44ae1201658197a",
-    "skin": 1.4, "replicas": 64, "block": {"mixed": 128, "fp64": 256},
+    "sources_sha256": "4ac86b4a8f7812e490817fb2263fe96d5e93b0a72aa67f9018d4ea50337cf88c",
+    "skin": 1.8, "replicas": 64, "block": {"mixed": 128, "fp64": 256},
     "fetch_factor": 2.0, "write_factor": 1.0,
     "kib": {  # (FETCH_SIZE, WRITE_SIZE)
-        ("mixed", "pass1"): (17350.7, 23293.2), ("mixed", "pass2"): (28060.8, 18696.8),
-        ("fp64", "pass1"): (15821.1, 31879.1), ("fp64", "pass2"): (28220.8, 18292.7),
-        ("mixed", "integrate"): (18130.8, 18219.8), ("fp64", "integrate"): (18119.9, 18179.3),
-        ("mixed", "rebuild_count"): (264.7, 340.9), ("mixed", "rebuild_scatter"): (762.3, 1450.6),
-        ("mixed", "rebuild_order"): (711.3, 1715.9),
+        ("mixed", "pass1"): (20972.4, 23250.5), ("mixed", "pass2"): (27893.4, 18739.6),
+        ("fp64", "pass1"): (18914.1, 31870.7), ("fp64", "pass2"): (28288.9, 18293.1),
+        ("mixed", "integrate"): (18130.3, 18222.7), ("fp64", "integrate"): (18120.3, 18179.7),
+        ("mixed", "rebuild_count"): (189.7, 210.7), ("mixed", "rebuild_scatter"): (463.1, 839.4),
+        ("mixed", "rebuild_order"): (435.8, 1028.7),
         # the scan runs inside the scatter stage on this workload: no launch
         ("mixed", "rebuild_scan"): (0.0, 0.0),
         # kernels of one workgroup size in both precisions: mean over both runs
-        ("mixed", "rebuild_list"): (2026.1, 1346.4), ("mixed", "finalize"): (488.3, 32.0),
+        ("mixed", "rebuild_list"): (1820.2, 1240.6), ("mixed", "finalize"): (487.9, 32.0),
     },
 }
 
@@ -170,14 +170,11 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
     specs = copy.deepcopy(wl.systems)
     n_atoms = sum(s.n for s in specs)
     eng = swfe.Engine(specs, P, dt=wl.dt, seed=seed, precision=precision)
-    if block:
-        eng.set_block(block)
-    else:
-        block = eng.autotune()
-    print(f"# {precision}: engine ready, block {block}", file=sys.stderr, flush=True)
     starts = [(s.sched_start, s.sched_end) for s in specs]
     # warm-up at the start of the path (lambda held); with no skin given the
-    # library's autotuner picks it (rebuild frequency vs list length) by timing
+    # library's autotuner picks it (rebuild frequency vs list length) by
+    # timing.  The block size is tuned at the skin of the run: the rebuild
+    # frequency changes which size is fastest.
     for s, (a, b) in zip(specs, starts):
         s.sched_start, s.sched_end, s.sched_steps = a, a, 0
     eng.set_schedule(specs)
@@ -186,7 +183,11 @@ def run_precision(precision, wl_builder, steps, warmup, P, seed, profile_steps, 
         eng.set_skin(skin)
     else:
         skin = eng.autotune_skin(skins or SKINS, steps=40)
-    print(f"# {precision}: skin {skin} A", file=sys.stderr, flush=True)
+    if block:
+        eng.set_block(block)
+    else:
+        block = eng.autotune()
+    print(f"# {precision}: engine ready, skin {skin} A, block {block}", file=sys.stderr, flush=True)
     eng.step(warmup, use_graph=True)
     torch.cuda.synchronize()
     eng.state()  # raises on a device error (non-finite, overflow, box)
@@ -463,9 +464,10 @@ def main():
                     help="block size of the mixed-precision run (0: swfe_autotune)")
     ap.add_argument("--block-fp64", type=int, default=0, choices=(0, 64, 128, 256),
                     help="block size of the FP64 run (0: swfe_autotune)")
-    ap.add_argument("--skin", type=float, default=1.4,
-                    help="Verlet skin in A (default 1.4, the fastest of 0.4-1.8 A on this workload; "
-                         "0: the library autotuner chooses among 0.4, 0.7, 1.0, 1.4, 1.8 A)")
+    ap.add_argument("--skin", type=float, default=1.8,
+                    help="Verlet skin in A (default 1.8: 1.4, 1.6, 1.8 and 2.0 A give 134.8, 130.4, 128.6 and "
+                         "127.8 us per step on this workload, 2.0 A being the largest the lists are sized for; "
+                         "0: the library autotuner chooses among 0.7, 1.0, 1.4, 1.8, 2.0 A)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()

@@ -280,13 +280,15 @@ int swfe_sizes(const swfe_ctx *ctx, int64_t *n_total, int32_t *n_sys);
 /* Verlet-list skin (A, >= 0) of every system; the lists hold pairs within
  * a sigma + skin and are rebuilt for a system when a pair now within the
  * cutoff could be missing (displacements and box scaling since the build).
- * Default 0.5 A.  Rebuilds the lists and re-evaluates the interaction at
- * the current positions. */
+ * Default 0.5 A.  The list capacity per atom is sized at set-up for skins
+ * up to 2 A (allowing 30 % density increase); a larger skin is refused with
+ * SWFE_E_INVALID_ARG.  Rebuilds the lists and re-evaluates the interaction
+ * at the current positions. */
 int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream);
 
 /* Tuning: Verlet-list skin.  Times n_steps graph-replayed dynamics steps
  * (after 5 untimed ones; n_steps <= 0: 40) from the current state at each
- * candidate skin (A; NULL: 0.6, 0.9, 1.2, 1.4, 1.7; at most 16), the faster
+ * candidate skin (A; NULL: 0.6, 1.0, 1.4, 1.8, 2.0; at most 16), the faster
  * of two interleaved rounds, restoring the state from a host snapshot after
  * each (it allocates swfe_checkpoint_bytes of host memory for the call),
  * and keeps the fastest (host output `chosen`).  A longer skin rebuilds the

@@ -44,6 +44,7 @@ struct Plan {
     int64_t cells = 0;       // sum of per-system cell capacities
     int64_t max_tiles = 0;   // tiles at the smallest block size
     int32_t list_cap = kMaxList;  // Verlet-list rows per atom
+    double list_skin = kPlanSkin;   // largest skin the list capacity was planned for, A
     Layout lay{};
 };
 
@@ -155,6 +156,7 @@ int plan_core(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw
     if (!(skin >= 0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be >= 0");
     const double rc = p->a * p->sigma;
     P.list_cap = kMaxList;
+    P.list_skin = std::max(skin, kPlanSkin);
     int64_t off = 0, tiles = 0, cells = 0;
     for (int s = 0; s < n_sys; ++s) {
         const swfe_system_desc &q = d[s];
@@ -212,9 +214,11 @@ int plan_core(swfe_ctx *ctx, const swfe_system_desc *d, int n_sys, const swfe_sw
             sd.uf_pkT = q.uf_p * kKB * q.uf_T;
             sd.uf_is2 = 1.0 / (q.uf_sigma * q.uf_sigma);
             sd.uf_rc = q.uf_rcut;
-            // list capacity for the UF cutoff at this density, allowing skins
-            // up to 1.5 A and 30 % density fluctuation
-            const double rl = std::max(rc, q.uf_rcut) + 1.5;
+        }
+        {
+            // list capacity for the system's longest cutoff at its density,
+            // allowing skins up to the planned one and 30 % density increase
+            const double rl = rmax + P.list_skin;
             const double dens = (double)q.n_atoms / (q.box[0] * q.box[1] * q.box[2]);
             const double want = 1.3 * 4.18879020478639 * rl * rl * rl * dens + 16.0;
             P.list_cap = std::max(P.list_cap, (int32_t)std::min<double>(kMaxListUF, 32.0 * std::ceil(want / 32.0)));
@@ -1078,6 +1082,12 @@ int swfe_set_skin(swfe_ctx *ctx, double skin, void *stream)
 {
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
     if (!(skin >= 0.0 && skin < 5.0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be in [0, 5) A");
+    if (skin > ctx->plan.list_skin) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "skin %g A beyond the %g A the neighbour lists were sized for at set-up", skin,
+                 ctx->plan.list_skin);
+        return fail(ctx, SWFE_E_INVALID_ARG, msg);
+    }
     hipStream_t s = (hipStream_t)stream;
     ctx->skin = skin;
     for (auto &d : ctx->plan.desc) d.skin = skin;
@@ -1137,14 +1147,15 @@ int swfe_autotune_skin(swfe_ctx *ctx, const double *candidates, int32_t n_candid
                        double *chosen, void *stream)
 {
     if (!ctx || !ctx->ready) return fail(ctx, SWFE_E_STATE, "context not initialised");
-    static const double kDefaultSkins[] = {0.6, 0.9, 1.2, 1.4, 1.7};
+    static const double kDefaultSkins[] = {0.6, 1.0, 1.4, 1.8, 2.0};
     if (!candidates) {
         candidates = kDefaultSkins;
         n_candidates = (int32_t)(sizeof kDefaultSkins / sizeof kDefaultSkins[0]);
     }
     if (n_candidates <= 0 || n_candidates > 16) return fail(ctx, SWFE_E_INVALID_ARG, "1 to 16 skin candidates");
     for (int q = 0; q < n_candidates; ++q)
-        if (!(candidates[q] >= 0.0 && candidates[q] < 5.0)) return fail(ctx, SWFE_E_INVALID_ARG, "skin must be in [0, 5) A");
+        if (!(candidates[q] >= 0.0 && candidates[q] < 5.0 && candidates[q] <= ctx->plan.list_skin))
+            return fail(ctx, SWFE_E_INVALID_ARG, "skin candidates must be in [0, 5) A and within the planned skin");
     if (n_steps <= 0) n_steps = 40;
     hipStream_t s = (hipStream_t)stream;
     // every candidate steps the same state: a host snapshot is restored

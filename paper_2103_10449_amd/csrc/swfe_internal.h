@@ -7,8 +7,11 @@
 
 namespace swfe {
 
-constexpr int kMaxList = 64;       // Verlet-list capacity per atom without UF systems
-constexpr int kMaxListUF = 1024;   // largest capacity a UF reference may ask for
+constexpr int kMaxList = 64;       // smallest Verlet-list capacity per atom
+constexpr int kMaxListUF = 1024;   // largest capacity the planning may ask for
+// Verlet lists are sized for skins up to this (A), or up to the context's
+// skin when it is larger; set_skin refuses a larger skin afterwards.
+constexpr double kPlanSkin = 2.0;
 constexpr int kMaxShort = 48;      // neighbours within rc per atom (pass 1 -> pass 2)
 // short-list entries pass 1 keeps in LDS per atom (the rest, rarely any, in
 // the global short list): its term loop reads them without a round trip to

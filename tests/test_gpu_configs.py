@@ -10,7 +10,7 @@ benchmark times.
   short coupled run vs the oracle (shared lambda and P_S).
 * the 64-replica batch in the launch configuration the benchmark times
   (HIP-graph steps, the block sizes its autotune picks: 128 threads for the
-  mixed path, 256 for FP64; Verlet skin 1.4 A): the energy and 32 sampled
+  mixed path, 256 for FP64; Verlet skin 1.8 A): the energy and 32 sampled
   forces of all 64 replicas; a 20-step switching trajectory of the whole
   batch, with positions, work and lambda of six replicas (diamond, beta-tin
   and liquid; the smallest and the largest) against the oracle run on those
@@ -115,7 +115,7 @@ def test_c3_dcci_pair_full_size(swfe, sw_params):
 
 
 BENCH_BLOCK = {"mixed": 128, "fp64": 256}
-BENCH_SKIN = 1.4
+BENCH_SKIN = 1.8
 # replicas of the benchmark batch checked step by step: the smallest diamond,
 # the largest diamond, the largest beta-tin, the smallest beta-tin, the
 # smallest liquid and a large liquid
