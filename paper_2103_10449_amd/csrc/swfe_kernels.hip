@@ -900,22 +900,38 @@ __device__ __forceinline__ void list_block(const Ctl &c, const DevPtrs &p, const
     const int64_t N = c.n_total;
     const int s = tile.start + (valid ? a_loc : 0);
     const double4 xi = p.xs[s];
+    const float4 xif = p.xf[s];
     const int ci = cell_of_pos(xi, ibox, nc);
     const int cx = ci % nc[0], cy = (ci / nc[0]) % nc[1], cz = ci / (nc[0] * nc[1]);
     const int nxo = nc[0] >= 3 ? 3 : nc[0], nyo = nc[1] >= 3 ? 3 : nc[1], nzo = nc[2] >= 3 ? 3 : nc[2];
     const int x0c = nc[0] >= 3 ? cx - 1 : 0, y0c = nc[1] >= 3 ? cy - 1 : 0, z0c = nc[2] >= 3 ? cz - 1 : 0;
     const int32_t *start = p.cell_start + d.cell_base + sys;
     const int ncell = nxo * nyo * nzo;
-    // candidates of one chunk of up to 64 atoms of this lane's cell, as a mask
+    // Candidates of one chunk of up to 64 atoms of this lane's cell, as a
+    // mask, from the FP32 positions wrapped into the box, eight loads in
+    // flight: the test is conservative (the rounding of the wrapped FP32
+    // coordinates moves d^2 by far less than the margin), so the list holds
+    // every pair within rl and a few just beyond it, which the force passes'
+    // exact test drops.
+    const float bx = (float)box[0], by = (float)box[1], bz = (float)box[2];
+    const float ibx = (float)ibox[0], iby = (float)ibox[1], ibz = (float)ibox[2];
+    const double bmax = fmax(box[0], fmax(box[1], box[2]));
+    const float cut2 = (float)(rl2 * (1.0 + 1e-3) + 32.0 * rl * bmax * 1.1920928955078125e-7);
     auto chunk_mask = [&](int j0, int j1) {
         unsigned long long m = 0;
-        for (int j = j0; j < j1; ++j) {
-            if (j == s) continue;
-            const double4 xj = p.xs[j];
-            const double dx = min_image(xj.x - xi.x, box[0], ibox[0]);
-            const double dy = min_image(xj.y - xi.y, box[1], ibox[1]);
-            const double dz = min_image(xj.z - xi.z, box[2], ibox[2]);
-            if (dx * dx + dy * dy + dz * dz < rl2) m |= 1ull << (j - j0);
+        for (int jb = j0; jb < j1; jb += 8) {
+            float4 xj[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xj[u] = p.xf[jb + u < j1 ? jb + u : j1 - 1];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                float dx = xj[u].x - xif.x, dy = xj[u].y - xif.y, dz = xj[u].z - xif.z;
+                dx -= bx * rintf(dx * ibx);
+                dy -= by * rintf(dy * iby);
+                dz -= bz * rintf(dz * ibz);
+                const int j = jb + u;
+                if (j < j1 && j != s && dx * dx + dy * dy + dz * dz < cut2) m |= 1ull << (j - j0);
+            }
         }
         return m;
     };
