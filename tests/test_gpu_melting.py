@@ -24,8 +24,9 @@ meV/atom (crystal) and about 3.5 meV/atom (liquid legs).  At 15 GPa: T_m =
 1365.3 +- 1.1 K (paper 1365.3(3)); g(liquid) - g(beta-tin) = -0.001
 meV/atom at 1365.3 K, latent heat 0.140 eV/atom, liquid 17.05 A^3/atom
 against 16.60 for beta-tin.  A run whose trajectories differ only in
-rounding (the order of a reduction changed) gave 1684.0 +- 1.9 K and
-1361.0 +- 1.4 K: both melting points sit a few kelvin below the paper's."""
+rounding gave 1684.0 +- 1.9 K and 1361.0 +- 1.4 K, another 1683.5 +- 2.2 K
+and 1361.5 +- 1.7 K: both melting points sit a few kelvin below the
+paper's."""
 import numpy as np
 import pytest
 
