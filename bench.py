@@ -565,6 +565,17 @@ def main():
                            "hbm_frac": traffic / avg / PEAK_HBM if traffic else None,
                            "per_kernel_us": {k: 1e3 * v / n_prof for k, v in prof.items()},
                            "longest_kernel": max(prof, key=prof.get)}
+        # the other force pass against the same roofs
+        other = "pass2" if name == "pass1" else "pass1"
+        avg_o = prof[other] / n_prof / 1e3
+        fl_o = kernel_flops(other, mixed["n_atoms"], mixed["pairs"])
+        tr_o = measured_traffic(other, mixed["skin"], args.replicas, "mixed", mixed["block"])
+        out["roofline_" + other] = {"bound": "alu", "kernel": other, "achieved": fl_o / avg_o / 1e12,
+                                    "peak": PEAK["mixed"] / 1e12, "unit": "TFLOP/s",
+                                    "frac": fl_o / avg_o / PEAK["mixed"],
+                                    "frac_nonpacked": fl_o / avg_o / PEAK_FP32_NONPACKED,
+                                    "traffic": tr_o, "avg_launch_us": 1e6 * avg_o,
+                                    "hbm_frac": tr_o / avg_o / PEAK_HBM if tr_o else None}
         if fp64 is not None and fp64["prof"]:
             p64 = fp64["prof"]
             avg64 = p64[name] / n_prof / 1e3
