@@ -125,8 +125,14 @@ def test_skin_autotune_leaves_the_dynamics_where_they_were(swfe, sw_params):
 
 def test_skin_autotune_rejects_bad_candidates(swfe, sw_params):
     eng = swfe.Engine(copy.deepcopy(_specs()), sw_params)
-    for bad in ([], [1.0, -0.2], [6.0], [float("nan")], [0.5] * 17):
+    # 2.5 A: beyond the 2 A the neighbour lists were sized for at set-up
+    for bad in ([], [1.0, -0.2], [6.0], [float("nan")], [0.5] * 17, [1.0, 2.5]):
         with pytest.raises(swfe.SwfeError) as ei:
             eng.autotune_skin(bad)
         assert ei.value.code == swfe.E_INVALID_ARG
+    with pytest.raises(swfe.SwfeError) as ei:
+        eng.set_skin(2.5)
+    assert ei.value.code == swfe.E_INVALID_ARG
+    eng.set_skin(2.0)  # the largest the lists were sized for
+    eng.step(5)
     eng.close()
